@@ -1,0 +1,180 @@
+"""Benchmark: Split Bregman reconstructions per second at 256 x 256, 12 coils
+(line mask R = 4, 24 centre lines, TV + 3-level Daubechies-4, mu = 1e-3,
+lambda = gamma = 4e-3, 20 outer iterations, PCG tolerance 1e-3) with the
+circulant preconditioner, and PCG iterations to 1e-3 for none / circulant.
+
+One step = build the preconditioner + one full reconstruction of every slice
+of the batch (all rows of the hot path: spectrum build, system operator,
+preconditioner, PCG updates, Split Bregman steps).  Inputs are synthetic
+(seeded phantoms, coil maps, masks, noise) and resident in HBM before timing.
+
+Prints ONE JSON line.  Single GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1710_01758_amd import inputs as gen  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def apply_bytes(specs) -> int:
+    """Algorithmic HBM bytes of one apply_A over the batch: read x and the coil
+    maps, write y, 8 bytes per complex64 element: 8 N (N_c + 2) per slice."""
+    return int(sum(8 * s.m * s.n * (s.ncoils + 2) for s in specs))
+
+
+def time_apply_kernel(torch, ctx, xd, yd, reps=50):
+    """Average duration of the fused apply_A kernel, from HIP events recorded
+    on the library's stream around `reps` back-to-back launches."""
+    stream = torch.cuda.ExternalStream(ctx.stream) if ctx.stream else torch.cuda.current_stream()
+    for _ in range(5):
+        ctx.apply_A(xd, yd)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.apply_A(xd, yd)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3  # seconds
+
+
+def cpu_baseline(inst, n_outer_sample=2):
+    """The FP64 oracle (Algorithm 1 as written) on one 256^2 x 12 slice for a
+    bounded number of outer iterations, scaled to a full 20-iteration
+    reconstruction."""
+    from oracle import sb as osb
+    s = inst.spec
+    t0 = time.perf_counter()
+    osb.split_bregman(inst.kspace, inst.sens, inst.mask, s.mu, s.lam, s.gam, s.wavelet, s.levels,
+                      n_outer=n_outer_sample, tol=1e-3, precond="circulant")
+    dt = time.perf_counter() - t0
+    per_recon = dt * 20.0 / n_outer_sample
+    return {"value": 1.0 / per_recon, "unit": "recons/s", "cores": 1, "kind": "oracle",
+            "sample": f"one 256x256x12 slice, {n_outer_sample} of 20 outer iterations (FP64 NumPy, "
+                      f"single-threaded pocketfft), {dt:.2f} s, scaled x{20 / n_outer_sample:g}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=32, help="slices reconstructed per step")
+    ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1710_01758_amd import binding as B
+
+    B.lib()
+    torch.cuda.set_device(0)
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=a.scale)
+    insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(a.batch)]
+    ctx, ksp = B.context_for(insts)
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(kind="circulant"):
+        ctx.build_preconditioner(kind)
+        iters, _ = ctx.split_bregman_recon(ksp, x, n_outer=20, n_inner=1, tol=1e-3, maxit=1000)
+        return iters
+
+    log(f"bench: warmup {a.warmup} steps, batch {a.batch}")
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = None
+    for k in range(a.steps):
+        iters = step()
+        log(f"bench: step {k + 1}/{a.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = a.batch * a.steps / dt
+    ms_per_step = dt / a.steps * 1e3
+
+    # single-slice latency (one reconstruction alone)
+    ctx1, ksp1 = B.context_for(insts[:1])
+    x1 = torch.zeros(ctx1.image_elems, dtype=torch.complex64, device="cuda")
+    for _ in range(2):
+        ctx1.build_preconditioner("circulant")
+        ctx1.split_bregman_recon(ksp1, x1, n_outer=20)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n1 = 5
+    for _ in range(n1):
+        ctx1.build_preconditioner("circulant")
+        ctx1.split_bregman_recon(ksp1, x1, n_outer=20)
+    torch.cuda.synchronize()
+    single = n1 / (time.perf_counter() - t1)
+
+    # PCG iterations to 1e-3: none vs circulant (first slice, every solve)
+    it_none = step("none")
+    it_circ = step("circulant")
+
+    # roofline of the dominant kernel (fused apply_A)
+    xa = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    ya = torch.empty_like(xa)
+    t_apply = time_apply_kernel(torch, ctx, xa, ya)
+    bytes_apply = apply_bytes([i.spec for i in insts])
+    achieved = bytes_apply / t_apply / 1e9
+
+    out = {
+        "metric": "recons/s + PCG iters to 1e-3, 256^2 x 12 coils: circulant vs learned precond",
+        "value": round(value, 3),
+        "unit": "recons/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (fp32) with fp64 reductions",
+        "data": "synthetic",
+        "config": {"workload": f"split_bregman_recon 256x256, 12 coils, R=4 lines (24 centre), TV + db4 x3, "
+                               f"mu=1e-3 lambda=gamma=4e-3, 20 outer iters, PCG tol 1e-3, circulant; "
+                               f"batch of {a.batch} slices per step, data_scale {a.scale:g}",
+                   "global_batch": a.batch, "m": 256, "n": 256, "ncoils": 12, "parallelism": "none (1 GPU)"},
+        "single_slice_recons_per_s": round(single, 3),
+        "pcg_iters": {
+            "none": {"first_solve": int(it_none[0, 0]), "total_20_solves": int(it_none[:, 0].sum()),
+                     "per_solve": it_none[:, 0].tolist()},
+            "circulant": {"first_solve": int(it_circ[0, 0]), "total_20_solves": int(it_circ[:, 0].sum()),
+                          "per_solve": it_circ[:, 0].tolist()},
+        },
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_col_apply<256> (fused apply_A)", "avg_us": round(t_apply * 1e6, 2),
+                     "bytes_per_launch": bytes_apply},
+    }
+    if not a.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(insts[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

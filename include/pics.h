@@ -1,0 +1,169 @@
+/*
+ * pics.h -- C ABI of libpics.so: the preconditioned conjugate gradient (PCG)
+ * inner solve of Split Bregman for parallel-imaging + compressed-sensing MRI,
+ * with the block-circulant-with-circulant-blocks (BCCB) preconditioner of
+ * Koolstra, van Gemert, Boernert, Webb and Remis, "Accelerating CS in Parallel
+ * Imaging Reconstructions Using an Efficient and Effective Circulant
+ * Preconditioner" (arXiv 1710.01758).  Built for AMD MI355X (gfx950).
+ *
+ * Problem (paper, Theory, Eq. original):
+ *   x^ = argmin mu/2 sum_i ||R F S_i x - y_i||^2 + ||D_x x||_1 + ||D_y x||_1 + ||W x||_1
+ * solved by Split Bregman (Algorithm 1), whose step 5 is A x = b (Eq. system):
+ *   A = mu sum_i (R F S_i)^H R F S_i + lambda (D_x^H D_x + D_y^H D_y) + gamma W^H W,
+ * preconditioned by M^{-1} = F^H diag(k)^{-1} F with k = diag(F A F^H)
+ * (Eqs. K, precon, Kdiag).
+ *
+ * Conventions shared by every entry point
+ *   - complex data are interleaved float32 pairs (re, im), "c64".
+ *   - an image is [m][n], row-major, n contiguous; axis 0 (length m) is the
+ *     phase-encode axis that a line mask selects.  F is the unitary 2D DFT,
+ *     DC at [0][0] (no fftshift).
+ *   - a context holds a batch of nslices independent slices; image-shaped
+ *     buffers pack the slices one after another (slice s starts at element
+ *     sum_{s'<s} m_s' n_s'), coil-shaped buffers pack [nc_s][m_s][n_s] per
+ *     slice, masks pack uint8[m_s] (line masks) per slice.
+ *     pics_sizes() returns the packed totals.
+ *   - every data pointer is a device pointer owned by the caller; sizes are
+ *     element counts.  The context borrows `sens` and `masks` until
+ *     pics_destroy() and owns its workspace (allocated once in pics_create;
+ *     no other call allocates device memory).
+ *   - calls are ordered on the stream given at creation and asynchronous
+ *     unless they return host results (those synchronise that stream).
+ *     One host thread per context at a time.
+ *   - return value: 0 = OK, > 0 = warning, < 0 = error (see PICS_*).  Errors
+ *     detected on the host are reported before anything is launched; the
+ *     library never aborts.  pics_last_error() gives a message.
+ */
+#ifndef PICS_H
+#define PICS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PICS_OK 0
+#define PICS_WARN_MAXIT 1        /* a PCG solve stopped at maxit without reaching tol */
+#define PICS_WARN_FALLBACK 2     /* learned spectrum rejected (k <= 0 or not finite); circulant used */
+#define PICS_ERR_INVALID (-1)    /* bad argument (null pointer, size, parameter) */
+#define PICS_ERR_UNSUPPORTED (-2)/* size without an FFT plan, mask kind or wavelet not available */
+#define PICS_ERR_NONFINITE (-3)  /* non-finite scalar inside PCG */
+#define PICS_ERR_BREAKDOWN (-4)  /* p^H A p <= 0 inside PCG */
+#define PICS_ERR_NOT_POSITIVE (-5)/* circulant spectrum k has a non-positive entry */
+#define PICS_ERR_HIP (-6)        /* HIP runtime error */
+#define PICS_ERR_STATE (-7)      /* call needs a preconditioner that was not built */
+
+#define PICS_MASK_LINES 0        /* uint8[m]: k-space row u sampled (all of axis 1) */
+#define PICS_MASK_2D 1           /* uint8[m][n] (not available in this build) */
+
+#define PICS_WAVELET_NONE 0
+#define PICS_WAVELET_HAAR 1
+#define PICS_WAVELET_DB4 2       /* 8-tap Daubechies, 4 vanishing moments, periodised */
+
+#define PICS_PRECOND_NONE 0
+#define PICS_PRECOND_JACOBI 1    /* diag(A)^{-1} (paper, Results: no gain) */
+#define PICS_PRECOND_CIRCULANT 2 /* F^H diag(k)^{-1} F, Eq. precon */
+#define PICS_PRECOND_LEARNED 3   /* circulant with k multiplied by a caller-given correction */
+
+#define PICS_TERM_DATA 1         /* mu sum_i (R F S_i)^H R F S_i */
+#define PICS_TERM_TV 2           /* lambda (D_x^H D_x + D_y^H D_y), periodic backward differences */
+#define PICS_TERM_GAMMA 4        /* gamma W^H W = gamma I (W unitary) */
+#define PICS_TERM_ALL 7
+
+/* One slice.  m, n in {64, 128, 192, 224, 256, 320, 512}; ncoils >= 1;
+ * levels: wavelet levels (each level needs even extents); mu, lambda,
+ * gamma >= 0 and finite (Split Bregman needs lambda, gamma > 0: its shrink
+ * thresholds are 1/lambda and 1/gamma, Algorithm 1 steps 6-8). */
+typedef struct pics_desc {
+  int32_t m, n, ncoils;
+  int32_t mask_kind;
+  int32_t wavelet, levels;
+  double mu, lambda, gamma;
+} pics_desc;
+
+typedef struct pics_ctx pics_ctx;
+
+/* Create a context for nslices slices.  sens: packed coil sensitivities
+ * S_i (c64, [nc][m][n] per slice; the paper normalises them so that
+ * sum_i |S_i|^2 = 1, Methods, Coil sensitivity maps); masks: packed binary
+ * masks R.  stream: a hipStream_t (NULL = default stream).
+ * Returns PICS_ERR_INVALID / PICS_ERR_UNSUPPORTED for descriptors it cannot
+ * serve, PICS_ERR_HIP if allocation fails. */
+int pics_create(pics_ctx** ctx, int32_t nslices, const pics_desc* descs, const void* sens, const uint8_t* masks,
+                void* stream);
+int pics_destroy(pics_ctx* ctx);
+
+/* Packed element counts: image-shaped (c64 elements), coil-shaped (c64
+ * elements) and mask bytes. */
+int pics_sizes(const pics_ctx* ctx, int64_t* image_elems, int64_t* coil_elems, int64_t* mask_bytes);
+
+/* Build the preconditioner (paper, Efficient Implementation of the
+ * Preconditioner, Eqs. d and diagonalelements; Table 1 lists its cost):
+ * k = mu k_c + lambda k_d + gamma, k_c(j) = (1/N^2) sum_l r(l) P(l - j) with
+ * P = sum_i |DFT(s_i)|^2, k_d the symbol of the periodic Laplacian.
+ * kind: PICS_PRECOND_*.  correction: float per pixel (image-packed),
+ * required for LEARNED (k <- k * correction), else ignored.  khat_out:
+ * optional float per pixel receiving k.  Synchronises the stream.  Returns
+ * PICS_ERR_NOT_POSITIVE if k has an entry <= 0 (e.g. gamma = 0 with the DC
+ * line unsampled); for LEARNED a rejected correction falls back to the
+ * circulant k with PICS_WARN_FALLBACK. */
+int build_preconditioner(pics_ctx* ctx, int32_t kind, const float* correction, float* khat_out);
+
+/* y = A x for every slice (Eq. system); terms selects PICS_TERM_* parts.
+ * x and y image-packed c64, must not alias. */
+int apply_A(pics_ctx* ctx, const void* x, void* y, int32_t terms);
+
+/* z = M^{-1} r = F^H diag(k)^{-1} F r (Eq. precon); needs a CIRCULANT or
+ * LEARNED build.  r and z image-packed c64, must not alias. */
+int apply_Minv(pics_ctx* ctx, const void* r, void* z);
+
+/* Unnormalised 2D DFT of every slice: out = sum exp(-+2 pi i (u i / m + v j / n)) in.
+ * inverse = 0: forward (minus sign), 1: inverse (plus sign, no 1/N). */
+int pics_fft2(pics_ctx* ctx, const void* in, void* out, int32_t inverse);
+
+/* Orthonormal periodised wavelet transform W (inverse = 0) or W^H
+ * (inverse = 1) per slice, Mallat layout, `levels` levels (paper, Theory:
+ * W unitary).  in and out image-packed c64, must not alias. */
+int pics_wavelet(pics_ctx* ctx, const void* in, void* out, int32_t inverse);
+
+/* Solve A x = b by PCG with the preconditioner of the last build (none if
+ * never built): paper, Complexity section (left preconditioning; equivalent
+ * to standard PCG for Hermitian positive definite A and M).  x holds x0 on
+ * entry and the solution on exit.  Stops per slice when the recursive
+ * residual satisfies ||r|| <= tol ||b|| or after maxit iterations
+ * (iteration = one product A p).  maxit_per_slice (host, nslices entries,
+ * optional) overrides maxit per slice; with tol = 0 it fixes the iteration
+ * count exactly.  Vectors are FP32, inner products and alpha / beta FP64.
+ * Host outputs (optional, nslices entries each): iterations, final relative
+ * residual, status (1 converged, 0 stopped at the cap, < 0 error).
+ * Returns PICS_WARN_MAXIT if a slice stopped at the cap with tol > 0. */
+int pcg_solve(pics_ctx* ctx, const void* b, void* x, double tol, int32_t maxit, const int32_t* maxit_per_slice,
+              int32_t* iters_host, double* relres_host, int32_t* status_host);
+
+/* Split Bregman reconstruction (Algorithm 1) of every slice from zero-filled
+ * k-space y (coil-packed c64; samples outside the mask are ignored).
+ * x^[1] = root sum of squares of the coil images; n_outer outer and n_inner
+ * inner iterations; each step-5 solve is pcg_solve with the current
+ * preconditioner, warm-started from the latest x.  lock_iters (host,
+ * optional, [n_outer * n_inner][nslices]) fixes the PCG iteration count of
+ * each solve (tol ignored).  x_out: image-packed c64 result.  pcg_iters
+ * (host, optional, [n_outer * n_inner][nslices]) receives the counts. */
+int split_bregman_recon(pics_ctx* ctx, const void* kspace, int32_t n_outer, int32_t n_inner, double tol,
+                        int32_t maxit, const int32_t* lock_iters, void* x_out, int32_t* pcg_iters);
+
+/* Options: PICS_OPT_POLL_CHUNK = PCG iterations enqueued between host
+ * convergence polls (first poll; later polls double it, up to 32). */
+#define PICS_OPT_POLL_CHUNK 1
+int pics_set_option(pics_ctx* ctx, int32_t key, int64_t value);
+
+const char* pics_status_string(int status);
+const char* pics_last_error(const pics_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PICS_H */

@@ -1,0 +1,216 @@
+"""Thin ctypes binding of libpics.so (argument marshalling only).
+
+Every computation runs in the native library; this module converts Python
+arguments to the C ABI of include/pics.h.  Device buffers are torch tensors on
+a ROCm device (torch is used for device memory and streams only).  Loading
+fails loudly if the library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpics.so")
+
+PICS_OK = 0
+PICS_WARN_MAXIT = 1
+PICS_WARN_FALLBACK = 2
+MASK_LINES, MASK_2D = 0, 1
+WAVELET = {"none": 0, "haar": 1, "db4": 2}
+PRECOND = {"none": 0, "jacobi": 1, "circulant": 2, "learned": 3}
+TERM_DATA, TERM_TV, TERM_GAMMA, TERM_ALL = 1, 2, 4, 7
+OPT_POLL_CHUNK = 1
+
+
+class PicsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pics error {code}: {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("ncoils", ctypes.c_int32),
+                ("mask_kind", ctypes.c_int32), ("wavelet", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("mu", ctypes.c_double), ("lam", ctypes.c_double), ("gam", ctypes.c_double)]
+
+
+_LIB = None
+
+EXPORTS = ["pics_create", "pics_destroy", "pics_sizes", "build_preconditioner", "apply_A", "apply_Minv",
+           "pics_fft2", "pics_wavelet", "pcg_solve", "split_bregman_recon", "pics_set_option",
+           "pics_status_string", "pics_last_error"]
+
+
+def lib(path: str = LIB_PATH):
+    """Load libpics.so (raises if it is not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_1710_01758_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pi32, pdbl, pi64 = ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(i64)
+    sig = {
+        "pics_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(Desc), vp, vp, vp]),
+        "pics_destroy": (ctypes.c_int, [vp]),
+        "pics_sizes": (ctypes.c_int, [vp, pi64, pi64, pi64]),
+        "build_preconditioner": (ctypes.c_int, [vp, i32, vp, vp]),
+        "apply_A": (ctypes.c_int, [vp, vp, vp, i32]),
+        "apply_Minv": (ctypes.c_int, [vp, vp, vp]),
+        "pics_fft2": (ctypes.c_int, [vp, vp, vp, i32]),
+        "pics_wavelet": (ctypes.c_int, [vp, vp, vp, i32]),
+        "pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, i32, pi32, pi32, pdbl, pi32]),
+        "split_bregman_recon": (ctypes.c_int, [vp, vp, i32, i32, dbl, i32, pi32, vp, pi32]),
+        "pics_set_option": (ctypes.c_int, [vp, i32, i64]),
+        "pics_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "pics_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _i32(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Context:
+    """A batch of slices sharing one stream.  `descs` are (m, n, ncoils,
+    wavelet name, levels, mu, lambda, gamma) records; `sens` (complex64) and
+    `masks` (uint8) are packed device tensors kept alive by this object."""
+
+    def __init__(self, descs: Sequence[dict], sens, masks, stream=None):
+        import torch
+        self.L = lib()
+        self.n = len(descs)
+        arr = (Desc * self.n)()
+        for i, d in enumerate(descs):
+            arr[i] = Desc(int(d["m"]), int(d["n"]), int(d["ncoils"]), MASK_LINES if d.get("mask_kind", "lines") == "lines" else MASK_2D,
+                          WAVELET[d.get("wavelet", "db4")], int(d.get("levels", 0)), float(d["mu"]),
+                          float(d["lam"]), float(d["gam"]))
+        self.descs = list(descs)
+        self._keep = (sens, masks)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.L.pics_create(ctypes.byref(h), self.n, arr, _ptr(sens), _ptr(masks), ctypes.c_void_p(stream))
+        if rc != PICS_OK:
+            raise PicsError(rc, self.L.pics_status_string(rc).decode())
+        self.h = h
+        img, coil, mk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.L.pics_sizes(self.h, ctypes.byref(img), ctypes.byref(coil), ctypes.byref(mk))
+        self.image_elems, self.coil_elems, self.mask_bytes = img.value, coil.value, mk.value
+
+    # -- helpers
+    def _check(self, rc: int, allow_warn: bool = True) -> int:
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise PicsError(rc, self.L.pics_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pics_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key: int, value: int):
+        return self._check(self.L.pics_set_option(self.h, key, value))
+
+    # -- entry points (same names as the C ABI)
+    def build_preconditioner(self, kind: str = "circulant", correction=None, khat=None) -> int:
+        return self._check(self.L.build_preconditioner(self.h, PRECOND[kind], _ptr(correction), _ptr(khat)))
+
+    def apply_A(self, x, y, terms: int = TERM_ALL) -> int:
+        return self._check(self.L.apply_A(self.h, _ptr(x), _ptr(y), terms))
+
+    def apply_Minv(self, r, z) -> int:
+        return self._check(self.L.apply_Minv(self.h, _ptr(r), _ptr(z)))
+
+    def fft2(self, x, out, inverse: bool = False) -> int:
+        return self._check(self.L.pics_fft2(self.h, _ptr(x), _ptr(out), int(inverse)))
+
+    def wavelet(self, x, out, inverse: bool = False) -> int:
+        return self._check(self.L.pics_wavelet(self.h, _ptr(x), _ptr(out), int(inverse)))
+
+    def pcg_solve(self, b, x, tol: float, maxit: int, maxit_per_slice=None):
+        iters = np.zeros(self.n, np.int32)
+        relres = np.zeros(self.n, np.float64)
+        status = np.zeros(self.n, np.int32)
+        mp = _i32(maxit_per_slice)
+        rc = self.L.pcg_solve(self.h, _ptr(b), _ptr(x), float(tol), int(maxit), mp[1] if mp else None,
+                              iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              relres.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self._check(rc)
+        return iters, relres, status, rc
+
+    def split_bregman_recon(self, kspace, x_out, n_outer: int = 20, n_inner: int = 1, tol: float = 1e-3,
+                            maxit: int = 1000, lock=None):
+        iters = np.zeros((n_outer * n_inner, self.n), np.int32)
+        lk = _i32(None if lock is None else np.asarray(lock).reshape(n_outer * n_inner, self.n))
+        rc = self.L.split_bregman_recon(self.h, _ptr(kspace), n_outer, n_inner, float(tol), int(maxit),
+                                        lk[1] if lk else None, _ptr(x_out),
+                                        iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self._check(rc)
+        return iters, rc
+
+
+# ---------------------------------------------------------------------------
+# packing of host arrays into the library's layouts (marshalling only)
+
+def spec_desc(spec) -> dict:
+    return dict(m=spec.m, n=spec.n, ncoils=spec.ncoils, mask_kind=spec.mask_kind, wavelet=spec.wavelet,
+                levels=spec.levels if spec.wavelet != "none" else 0, mu=spec.mu, lam=spec.lam, gam=spec.gam)
+
+
+def pack_images(arrs: Sequence[np.ndarray]) -> np.ndarray:
+    return np.concatenate([np.asarray(a, np.complex64).ravel() for a in arrs])
+
+
+def unpack_images(flat: np.ndarray, shapes: Sequence[tuple]) -> List[np.ndarray]:
+    out, o = [], 0
+    for (m, n) in shapes:
+        out.append(flat[o:o + m * n].reshape(m, n))
+        o += m * n
+    return out
+
+
+def pack_masks(masks: Sequence[np.ndarray]) -> np.ndarray:
+    return np.concatenate([np.asarray(mk, np.uint8).ravel() for mk in masks])
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def context_for(instances, device="cuda", stream=None):
+    """Create a Context for a list of inputs.Instance; returns (ctx, kspace_dev)."""
+    sens = to_device(pack_images([inst.sens for inst in instances]), device)
+    masks = to_device(pack_masks([inst.mask for inst in instances]), device)
+    ctx = Context([spec_desc(inst.spec) for inst in instances], sens, masks, stream)
+    ksp = to_device(pack_images([inst.kspace for inst in instances]), device)
+    return ctx, ksp

@@ -1,0 +1,617 @@
+// Host side of libpics.so: context, validation, workspace and the
+// orchestration of the kernels behind the C ABI declared in include/pics.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pics.h"
+#include "fft.hpp"
+#include "internal.hpp"
+
+using namespace pics;
+
+struct pics_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int nslices = 0;
+  std::vector<pics_desc> desc;
+  std::vector<SliceDev> sl;
+  long long img_total = 0, coil_total = 0, mask_total = 0, aux_total = 0, max_pixels = 0;
+  int max_levels = 0;
+  bool any_wavelet = false, any_nowavelet = false;
+
+  struct Group {
+    int m, n;
+    std::vector<int> idx;
+    int* idx_dev;
+  };
+  std::vector<Group> groups;
+  int* all_idx_dev = nullptr;
+
+  const float2* sens = nullptr;
+  const uint8_t* masks = nullptr;
+
+  // one device block for everything the context owns
+  void* block = nullptr;
+  SliceDev* sl_dev = nullptr;
+  float2* tw = nullptr;
+  float2 *r, *t, *z, *p, *pn, *q, *g1, *g, *rhs, *bx, *by, *bw, *ux, *uy, *uw, *w1, *w2;
+  float2* coiltmp = nullptr;
+  float *kraw, *kinv, *jac;
+  double *part, *pbar;
+  PcgState* st = nullptr;
+  int* bad = nullptr;
+  int* lock_dev = nullptr;
+  int lock_cap = 0;  // ints available at lock_dev (grown on demand by split_bregman_recon)
+  void* lock_block = nullptr;
+
+  PcgState* st_host = nullptr;  // pinned
+  int* flag_host = nullptr;      // pinned
+  int pk = PK_NONE;
+  int poll_chunk = 2;
+  std::string err;
+};
+
+namespace {
+
+int fail(pics_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fail(ctx, PICS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+Ws make_ws(const pics_ctx* c) {
+  Ws w;
+  w.sl = c->sl_dev;
+  w.group = c->all_idx_dev;
+  w.sens = c->sens;
+  w.mask = c->masks;
+  w.tw = c->tw;
+  w.kinv = c->kinv;
+  w.jac = c->jac;
+  w.part = c->part;
+  w.st = c->st;
+  return w;
+}
+
+Launch make_launch(const pics_ctx* c, const pics_ctx::Group& g) {
+  Launch L;
+  L.stream = c->stream;
+  L.m = g.m;
+  L.n = g.n;
+  L.count = (int)g.idx.size();
+  L.group = g.idx_dev;
+  return L;
+}
+
+Simple make_simple(const pics_ctx* c) {
+  Simple S;
+  S.stream = c->stream;
+  S.nslices = c->nslices;
+  S.max_pixels = c->max_pixels;
+  return S;
+}
+
+// Ws whose group table is the group's slice list (grid.y -> slice)
+Ws ws_for(const pics_ctx* c, const pics_ctx::Group& g) {
+  Ws w = make_ws(c);
+  w.group = g.idx_dev;
+  return w;
+}
+
+bool levels_ok(int m, int n, int levels) {
+  for (int l = 0; l < levels; ++l) {
+    if ((m >> l) % 2 || (n >> l) % 2 || (m >> l) < 2 || (n >> l) < 2) return false;
+  }
+  return true;
+}
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+}  // namespace
+
+// =====================================================================
+extern "C" {
+
+const char* pics_status_string(int s) {
+  switch (s) {
+    case PICS_OK: return "ok";
+    case PICS_WARN_MAXIT: return "warning: PCG reached maxit";
+    case PICS_WARN_FALLBACK: return "warning: learned spectrum rejected, circulant used";
+    case PICS_ERR_INVALID: return "invalid argument";
+    case PICS_ERR_UNSUPPORTED: return "unsupported size or mode";
+    case PICS_ERR_NONFINITE: return "non-finite value in PCG";
+    case PICS_ERR_BREAKDOWN: return "PCG breakdown (p^H A p <= 0)";
+    case PICS_ERR_NOT_POSITIVE: return "circulant spectrum not positive";
+    case PICS_ERR_HIP: return "HIP runtime error";
+    case PICS_ERR_STATE: return "preconditioner not built";
+    default: return "unknown status";
+  }
+}
+
+const char* pics_last_error(const pics_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
+  if (!c) return PICS_ERR_INVALID;
+  if (key == PICS_OPT_POLL_CHUNK) {
+    if (value < 1 || value > 1024) return fail(c, PICS_ERR_INVALID, "poll chunk out of range");
+    c->poll_chunk = (int)value;
+    return PICS_OK;
+  }
+  return fail(c, PICS_ERR_INVALID, "unknown option %d", key);
+}
+
+int pics_sizes(const pics_ctx* c, int64_t* img, int64_t* coil, int64_t* mask) {
+  if (!c) return PICS_ERR_INVALID;
+  if (img) *img = c->img_total;
+  if (coil) *coil = c->coil_total;
+  if (mask) *mask = c->mask_total;
+  return PICS_OK;
+}
+
+int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const void* sens, const uint8_t* masks,
+                void* stream) {
+  if (!out) return PICS_ERR_INVALID;
+  *out = nullptr;
+  if (nslices < 1 || nslices > 65535 || !descs || !sens || !masks) return PICS_ERR_INVALID;
+  for (int s = 0; s < nslices; ++s) {
+    const pics_desc& d = descs[s];
+    if (d.m <= 0 || d.n <= 0 || d.ncoils < 1 || d.ncoils > 4096) return PICS_ERR_INVALID;
+    if (!finite_nonneg(d.mu) || !finite_nonneg(d.lambda) || !finite_nonneg(d.gamma)) return PICS_ERR_INVALID;
+    if (d.wavelet < 0 || d.wavelet > 2 || d.levels < 0 || d.levels > 12) return PICS_ERR_INVALID;
+    if (d.mask_kind != PICS_MASK_LINES && d.mask_kind != PICS_MASK_2D) return PICS_ERR_INVALID;
+    if (d.mask_kind == PICS_MASK_2D) return PICS_ERR_UNSUPPORTED;
+    if (!fft_size_supported(d.m) || !fft_size_supported(d.n)) return PICS_ERR_UNSUPPORTED;
+    if (d.wavelet != PICS_WAVELET_NONE && !levels_ok(d.m, d.n, d.levels)) return PICS_ERR_UNSUPPORTED;
+  }
+  pics_ctx* c = new pics_ctx();
+  c->nslices = nslices;
+  c->stream = (hipStream_t)stream;
+  c->sens = (const float2*)sens;
+  c->masks = masks;
+  c->desc.assign(descs, descs + nslices);
+  hipGetDevice(&c->device);
+
+  std::map<std::pair<int, int>, int> gidx;
+  for (int s = 0; s < nslices; ++s) {
+    const pics_desc& d = descs[s];
+    SliceDev sd{};
+    sd.m = d.m;
+    sd.n = d.n;
+    sd.nc = d.ncoils;
+    sd.mask_kind = d.mask_kind;
+    sd.wavelet = d.wavelet;
+    sd.levels = d.wavelet == PICS_WAVELET_NONE ? 0 : d.levels;
+    sd.mu = (float)d.mu;
+    sd.lam = (float)d.lambda;
+    sd.gam = (float)d.gamma;
+    sd.img = c->img_total;
+    sd.coil = c->coil_total;
+    sd.mask = c->mask_total;
+    sd.aux = c->aux_total;
+    const long long N = (long long)d.m * d.n;
+    c->img_total += N;
+    c->coil_total += N * d.ncoils;
+    c->mask_total += d.mask_kind == PICS_MASK_LINES ? d.m : N;
+    c->aux_total += (long long)(d.n / kColT) * d.m;
+    c->max_pixels = std::max(c->max_pixels, N);
+    c->max_levels = std::max(c->max_levels, sd.levels);
+    if (sd.levels > 0) c->any_wavelet = true;
+    else c->any_nowavelet = true;
+    c->sl.push_back(sd);
+    auto key = std::make_pair(d.m, d.n);
+    auto it = gidx.find(key);
+    if (it == gidx.end()) {
+      gidx[key] = (int)c->groups.size();
+      c->groups.push_back({d.m, d.n, {s}, nullptr});
+    } else {
+      c->groups[it->second].idx.push_back(s);
+    }
+  }
+
+  // ---- one allocation for everything
+  const long long I = c->img_total;
+  std::vector<std::pair<void**, size_t>> plan;
+  auto add = [&](void** ptr, size_t bytes) { plan.push_back({ptr, (bytes + 255) / 256 * 256}); };
+  add((void**)&c->sl_dev, sizeof(SliceDev) * nslices);
+  add((void**)&c->all_idx_dev, sizeof(int) * nslices);
+  for (auto& g : c->groups) add((void**)&g.idx_dev, sizeof(int) * g.idx.size());
+  add((void**)&c->tw, sizeof(float2) * kTwiddleTotal);
+  float2** cbufs[] = {&c->r, &c->t, &c->z, &c->p, &c->pn, &c->q, &c->g1, &c->g, &c->rhs,
+                      &c->bx, &c->by, &c->bw, &c->ux, &c->uy, &c->uw, &c->w1, &c->w2};
+  for (float2** b : cbufs) add((void**)b, sizeof(float2) * I);
+  add((void**)&c->coiltmp, sizeof(float2) * c->coil_total);
+  add((void**)&c->kraw, sizeof(float) * I);
+  add((void**)&c->kinv, sizeof(float) * I);
+  add((void**)&c->jac, sizeof(float) * I);
+  add((void**)&c->part, sizeof(double) * nslices * kSlots * kPartMax);
+  add((void**)&c->pbar, sizeof(double) * std::max(1LL, c->aux_total));
+  add((void**)&c->st, sizeof(PcgState) * nslices);
+  add((void**)&c->bad, sizeof(int));
+  size_t total = 0;
+  for (auto& pr : plan) total += pr.second;
+  if (hipMalloc(&c->block, total) != hipSuccess) {
+    delete c;
+    return PICS_ERR_HIP;
+  }
+  char* base = (char*)c->block;
+  for (auto& pr : plan) {
+    *pr.first = base;
+    base += pr.second;
+  }
+  if (hipHostMalloc((void**)&c->st_host, sizeof(PcgState) * nslices, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->flag_host, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+    if (c->st_host) hipHostFree(c->st_host);
+    hipFree(c->block);
+    delete c;
+    return PICS_ERR_HIP;
+  }
+
+  // twiddles tw[k] = exp(-2 pi i k / N), computed in double
+  std::vector<float2> tw(kTwiddleTotal);
+  for (int N : kSupportedSizes) {
+    const int off = tw_offset(N);
+    for (int k = 0; k < N; ++k) {
+      const double a = -2.0 * M_PI * (double)k / (double)N;
+      tw[off + k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+  }
+  std::vector<int> all(nslices);
+  for (int s = 0; s < nslices; ++s) all[s] = s;
+  bool ok = hipMemcpy(c->tw, tw.data(), sizeof(float2) * kTwiddleTotal, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->sl_dev, c->sl.data(), sizeof(SliceDev) * nslices, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->all_idx_dev, all.data(), sizeof(int) * nslices, hipMemcpyHostToDevice) == hipSuccess;
+  for (auto& g : c->groups)
+    ok = ok && hipMemcpy(g.idx_dev, g.idx.data(), sizeof(int) * g.idx.size(), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemset(c->part, 0, sizeof(double) * nslices * kSlots * kPartMax) == hipSuccess;
+  if (!ok) {
+    hipHostFree(c->st_host);
+    hipHostFree(c->flag_host);
+    hipFree(c->block);
+    delete c;
+    return PICS_ERR_HIP;
+  }
+  *out = c;
+  return PICS_OK;
+}
+
+int pics_destroy(pics_ctx* c) {
+  if (!c) return PICS_ERR_INVALID;
+  hipStreamSynchronize(c->stream);
+  if (c->lock_block) hipFree(c->lock_block);
+  if (c->st_host) hipHostFree(c->st_host);
+  if (c->flag_host) hipHostFree(c->flag_host);
+  if (c->block) hipFree(c->block);
+  delete c;
+  return PICS_OK;
+}
+
+int build_preconditioner(pics_ctx* c, int32_t kind, const float* correction, float* khat_out) {
+  if (!c) return PICS_ERR_INVALID;
+  if (kind < PICS_PRECOND_NONE || kind > PICS_PRECOND_LEARNED) return fail(c, PICS_ERR_INVALID, "kind %d", kind);
+  if (kind == PICS_PRECOND_LEARNED && !correction) return fail(c, PICS_ERR_INVALID, "LEARNED needs a correction");
+  if (kind == PICS_PRECOND_NONE) {
+    c->pk = PK_NONE;
+    return PICS_OK;
+  }
+  const Ws w = make_ws(c);
+  int rc = PICS_OK;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const float* corr = (kind == PICS_PRECOND_LEARNED && attempt == 0) ? correction : nullptr;
+    for (auto& g : c->groups) HIPCHK(c, launch_col_coil_power(make_launch(c, g), ws_for(c, g), c->pbar, c->jac));
+    HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
+    HIPCHK(c, launch_build_k(make_simple(c), w, c->pbar, corr, c->kraw, c->kinv, c->jac, c->bad));
+    HIPCHK(c, hipMemcpyAsync(c->flag_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->flag_host[0]) break;
+    if (kind != PICS_PRECOND_LEARNED || attempt == 1) {
+      c->pk = PK_NONE;
+      return fail(c, PICS_ERR_NOT_POSITIVE, "circulant spectrum has an entry <= 0 or not finite");
+    }
+    rc = PICS_WARN_FALLBACK;  // retry without the correction
+    kind = PICS_PRECOND_CIRCULANT;
+  }
+  c->pk = kind;
+  if (khat_out)
+    HIPCHK(c, hipMemcpyAsync(khat_out, c->kraw, sizeof(float) * c->img_total, hipMemcpyDeviceToDevice, c->stream));
+  return rc;
+}
+
+int apply_A(pics_ctx* c, const void* x, void* y, int32_t terms) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!x || !y || x == y) return fail(c, PICS_ERR_INVALID, "apply_A: null or aliased buffers");
+  if (terms < 0 || terms > PICS_TERM_ALL) return fail(c, PICS_ERR_INVALID, "apply_A: terms %d", terms);
+  for (auto& g : c->groups)
+    HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, terms, c->pk, 0.0, (const float2*)x,
+                               nullptr, nullptr, nullptr, (float2*)y, nullptr, nullptr));
+  return PICS_OK;
+}
+
+int apply_Minv(pics_ctx* c, const void* r, void* z) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!r || !z || r == z) return fail(c, PICS_ERR_INVALID, "apply_Minv: null or aliased buffers");
+  if (c->pk != PK_CIRC && c->pk != PK_LEARNED) return fail(c, PICS_ERR_STATE, "apply_Minv: no circulant build");
+  for (auto& g : c->groups) HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 0, (const float2*)r, c->t));
+  for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 0, 0, 0.0, c->t));
+  for (auto& g : c->groups) HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 0, c->t, (float2*)z));
+  return PICS_OK;
+}
+
+int pics_fft2(pics_ctx* c, const void* in, void* out, int32_t inverse) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!in || !out) return fail(c, PICS_ERR_INVALID, "fft2: null buffer");
+  const int inv = inverse ? 1 : 0;
+  for (auto& g : c->groups)
+    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), inv, 0, (const float2*)in, c->t));
+  for (auto& g : c->groups) HIPCHK(c, launch_col_fft(make_launch(c, g), ws_for(c, g), inv, c->t, (float2*)out));
+  return PICS_OK;
+}
+
+int pics_wavelet(pics_ctx* c, const void* in, void* out, int32_t inverse) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!in || !out || in == out) return fail(c, PICS_ERR_INVALID, "wavelet: null or aliased buffers");
+  const Ws w = make_ws(c);
+  const Simple S = make_simple(c);
+  for (int s = 0; s < c->nslices; ++s) {
+    if (c->sl[s].levels == 0)
+      HIPCHK(c, hipMemcpyAsync((float2*)out + c->sl[s].img, (const float2*)in + c->sl[s].img,
+                               sizeof(float2) * c->sl[s].m * c->sl[s].n, hipMemcpyDeviceToDevice, c->stream));
+  }
+  WaveArgs a{};
+  a.mode = 0;
+  if (!inverse) {
+    for (int l = 0; l < c->max_levels; ++l) {
+      a.level = l;
+      a.inverse = 0;
+      a.pass = 0;
+      a.in = l == 0 ? (const float2*)in : c->w1;
+      a.out = c->w2;
+      HIPCHK(c, launch_wavelet(S, w, a));
+      a.pass = 1;
+      a.in = c->w2;
+      a.out = c->w1;
+      a.coef = (float2*)out;
+      HIPCHK(c, launch_wavelet(S, w, a));
+    }
+  } else {
+    for (int l = c->max_levels - 1; l >= 0; --l) {
+      a.level = l;
+      a.inverse = 1;
+      a.pass = 0;
+      a.in = c->w1;
+      a.coef = (float2*)in;
+      a.out = c->w2;
+      HIPCHK(c, launch_wavelet(S, w, a));
+      a.pass = 1;
+      a.in = c->w2;
+      a.out = l == 0 ? (float2*)out : c->w1;
+      HIPCHK(c, launch_wavelet(S, w, a));
+    }
+  }
+  return PICS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- PCG driver
+namespace {
+
+// Enqueue one PCG solve for every slice and wait for it.  When q_valid, q
+// already holds A x (the Split Bregman outer update computes it) and the
+// set-up product is skipped.
+int pcg_run(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, const int* maxit_dev, int maxit_max,
+            bool q_valid) {
+  const Ws w = make_ws(c);
+  const int pk = c->pk;
+  const bool circ = pk == PK_CIRC || pk == PK_LEARNED;
+  HIPCHK(c, launch_pcg_reset(c->stream, w, c->nslices, maxit, maxit_dev));
+  if (!q_valid)
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr,
+                                 nullptr, nullptr, c->q, nullptr, nullptr));
+  for (auto& g : c->groups)
+    HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
+                                c->t));
+  HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 1, x));
+  if (circ) {
+    for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
+    for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
+  }
+  const float2* zsrc = circ ? c->z : c->r;
+  int done_iters = 0;
+  int chunk = std::max(1, c->poll_chunk);
+  if (maxit_dev) chunk = std::max(1, maxit_max);  // iteration-locked: one poll at the end
+  while (true) {
+    const int todo = std::min(chunk, maxit_max - done_iters);
+    for (int k = 0; k < todo; ++k) {
+      for (auto& g : c->groups)
+        HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, c->p,
+                                   c->pn, c->q, nullptr, nullptr));
+      for (auto& g : c->groups)
+        HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, c->pn,
+                                    c->p, c->t));
+      if (circ) {
+        for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
+        for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
+      }
+    }
+    done_iters += std::max(todo, 0);
+    HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 0, x));
+    HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(PcgState) * c->nslices, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool all = true;
+    for (int s = 0; s < c->nslices; ++s) all = all && c->st_host[s].done;
+    if (all || done_iters >= maxit_max) break;
+    chunk = std::min(chunk * 2, 32);
+  }
+  int rc = PICS_OK;
+  for (int s = 0; s < c->nslices; ++s) {
+    const PcgState& st = c->st_host[s];
+    if (st.status < 0) rc = std::min(rc, st.status);
+    else if (rc >= 0 && st.status == 0 && tol > 0.0) rc = PICS_WARN_MAXIT;
+  }
+  if (rc < 0) return fail(c, rc, "PCG failed: %s", pics_status_string(rc));
+  return rc;
+}
+
+int ensure_lock(pics_ctx* c, long long count) {
+  if (count <= c->lock_cap) return PICS_OK;
+  if (c->lock_block) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipFree(c->lock_block));
+    c->lock_block = nullptr;
+    c->lock_cap = 0;
+  }
+  HIPCHK(c, hipMalloc(&c->lock_block, sizeof(int) * count));
+  c->lock_dev = (int*)c->lock_block;
+  c->lock_cap = (int)count;
+  return PICS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcg_solve(pics_ctx* c, const void* b, void* x, double tol, int32_t maxit, const int32_t* maxit_per_slice,
+              int32_t* iters_host, double* relres_host, int32_t* status_host) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!b || !x || b == x) return fail(c, PICS_ERR_INVALID, "pcg_solve: null or aliased buffers");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, PICS_ERR_INVALID, "pcg_solve: tol");
+  if (maxit < 0) return fail(c, PICS_ERR_INVALID, "pcg_solve: maxit");
+  int maxit_max = maxit;
+  const int* mdev = nullptr;
+  if (maxit_per_slice) {
+    maxit_max = 0;
+    for (int s = 0; s < c->nslices; ++s) {
+      if (maxit_per_slice[s] < 0) return fail(c, PICS_ERR_INVALID, "pcg_solve: maxit_per_slice");
+      maxit_max = std::max(maxit_max, (int)maxit_per_slice[s]);
+    }
+    int rc = ensure_lock(c, c->nslices);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->lock_dev, maxit_per_slice, sizeof(int) * c->nslices, hipMemcpyHostToDevice,
+                             c->stream));
+    mdev = c->lock_dev;
+  }
+  const int rc = pcg_run(c, (const float2*)b, (float2*)x, tol, maxit, mdev, maxit_max, false);
+  for (int s = 0; s < c->nslices; ++s) {
+    if (iters_host) iters_host[s] = c->st_host[s].iters;
+    if (relres_host) relres_host[s] = c->st_host[s].relres;
+    if (status_host) status_host[s] = c->st_host[s].status;
+  }
+  return rc;
+}
+
+int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_t n_inner, double tol,
+                        int32_t maxit, const int32_t* lock_iters, void* x_out, int32_t* pcg_iters) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!kspace || !x_out) return fail(c, PICS_ERR_INVALID, "split_bregman_recon: null buffer");
+  if (n_outer < 0 || n_inner < 1 || maxit < 0 || !(tol >= 0.0))
+    return fail(c, PICS_ERR_INVALID, "split_bregman_recon: iteration parameters");
+  for (int s = 0; s < c->nslices; ++s)
+    if (!(c->desc[s].lambda > 0.0) || !(c->desc[s].gamma > 0.0))
+      return fail(c, PICS_ERR_INVALID, "split_bregman_recon: lambda and gamma must be > 0 (shrink thresholds)");
+  const long long nsolve = (long long)n_outer * n_inner;
+  if (lock_iters) {
+    int rc = ensure_lock(c, std::max(1LL, nsolve * c->nslices));
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->lock_dev, lock_iters, sizeof(int) * nsolve * c->nslices, hipMemcpyHostToDevice,
+                             c->stream));
+  }
+  const Ws w = make_ws(c);
+  const Simple S = make_simple(c);
+  float2* x = (float2*)x_out;
+  // Algorithm 1, step 1: coil images F^H R y_i, root sum of squares, g_1
+  for (auto& g : c->groups)
+    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, (const float2*)kspace, c->coiltmp));
+  for (auto& g : c->groups) HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, x));
+  for (float2* b : {c->bx, c->by, c->bw, c->ux, c->uy, c->uw})
+    HIPCHK(c, launch_fill(c->stream, b, c->img_total, make_float2(0.f, 0.f)));
+  bool q_valid = false;
+  int rc_all = PICS_OK;
+  for (int jo = 0; jo < n_outer; ++jo) {
+    for (int ji = 0; ji < n_inner; ++ji) {
+      const long long solve = (long long)jo * n_inner + ji;
+      // step 4: b = g_j + lam [D_x^H (d_x - b_x) + D_y^H (d_y - b_y)] + gam W^H (d_w - b_w)
+      if (c->any_nowavelet) HIPCHK(c, launch_rhs_nowavelet(S, w, c->g, c->ux, c->uy, c->uw, c->rhs));
+      if (c->any_wavelet) {
+        WaveArgs a{};
+        a.mode = 1;
+        a.g = c->g;
+        a.ux = c->ux;
+        a.uy = c->uy;
+        a.rhs = c->rhs;
+        for (int l = c->max_levels - 1; l >= 0; --l) {
+          a.level = l;
+          a.inverse = 1;
+          a.pass = 0;
+          a.in = c->w1;
+          a.coef = c->uw;
+          a.out = c->w2;
+          HIPCHK(c, launch_wavelet(S, w, a));
+          a.pass = 1;
+          a.in = c->w2;
+          a.out = c->w1;
+          HIPCHK(c, launch_wavelet(S, w, a));
+        }
+      }
+      // step 5: PCG warm-started at x
+      int rc;
+      if (lock_iters) {
+        int mx = 0;
+        for (int s = 0; s < c->nslices; ++s) mx = std::max(mx, (int)lock_iters[solve * c->nslices + s]);
+        rc = pcg_run(c, c->rhs, x, 0.0, 0, c->lock_dev + solve * c->nslices, mx, q_valid);
+      } else {
+        rc = pcg_run(c, c->rhs, x, tol, maxit, nullptr, maxit, q_valid);
+      }
+      if (rc < 0) return rc;
+      if (rc > 0) rc_all = rc;
+      if (pcg_iters)
+        for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
+      // steps 6-11: TV and wavelet shrink / Bregman updates
+      HIPCHK(c, launch_tv_shrink(S, w, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+      if (c->any_wavelet) {
+        WaveArgs a{};
+        a.mode = 1;
+        a.bw = c->bw;
+        a.uw = c->uw;
+        for (int l = 0; l < c->max_levels; ++l) {
+          a.level = l;
+          a.inverse = 0;
+          a.pass = 0;
+          a.in = l == 0 ? x : c->w1;
+          a.out = c->w2;
+          HIPCHK(c, launch_wavelet(S, w, a));
+          a.pass = 1;
+          a.in = c->w2;
+          a.out = c->w1;
+          HIPCHK(c, launch_wavelet(S, w, a));
+        }
+      }
+      q_valid = false;
+    }
+    // steps 13-15 in the image domain: g_{j+1} = g_j + g_1 - A_data x; also q = A x
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_OUTER, TERM_ALL, c->pk, 0.0, x, nullptr,
+                                 nullptr, nullptr, c->q, c->g, c->g1));
+    q_valid = true;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return rc_all;
+}
+
+}  // extern "C"

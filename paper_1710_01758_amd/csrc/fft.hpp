@@ -1,0 +1,256 @@
+// Mixed-radix complex FFTs staged through LDS (gfx950).
+//
+// A length-N transform is carried by NT threads; thread t holds E = N / NT
+// elements in registers in the "cyclic" layout v[e] = element t + NT * e.
+// A plan is a list of radices R_1 .. R_s with product N, each dividing E.
+// Stage s (span Ns = R_1 ... R_{s-1}) is a self-sorting Stockham pass: the
+// thread computes E / R_s butterflies b = t + NT q, reading the cyclic inputs
+// v[q + r E/R_s], scaling input r by w_{Ns R}^{(b mod Ns) r}, applying an
+// in-register radix-R DFT and writing output r to position
+// (b / Ns) Ns R + (b mod Ns) + r Ns.  Between stages the outputs go through
+// LDS and come back in the cyclic layout; the last stage's outputs land
+// directly in the cyclic layout in registers, in natural frequency order.
+// No normalisation is applied (forward = exp(-2 pi i / N) kernel, inverse =
+// exp(+2 pi i / N)).
+#pragma once
+
+#include "common.hpp"
+
+namespace pics {
+
+// ----------------------------------------------------- twiddle multiplies
+
+// a * exp(DIR 2 pi i K / R), with the exact special cases of multiples of
+// 45 degrees.
+template <int R, int K, int DIR>
+__device__ __forceinline__ float2 tw_mul(float2 a) {
+  constexpr int k = ((K % R) + R) % R;
+  if constexpr (k == 0) {
+    return a;
+  } else if constexpr ((8 * k) % R == 0) {
+    constexpr int oct = (8 * k) / R;  // multiple of 45 degrees, 1..7
+    constexpr float h = 0.70710678118654752440f;
+    if constexpr (oct == 4) {
+      return make_float2(-a.x, -a.y);
+    } else if constexpr (oct == 2) {
+      return cmul_i(a, float(DIR));
+    } else if constexpr (oct == 6) {
+      return cmul_i(a, -float(DIR));
+    } else {
+      // (c + i DIR s) with |c| = |s| = h
+      constexpr float c = (oct == 1 || oct == 7) ? h : -h;
+      constexpr float s = (oct == 1 || oct == 3) ? h : -h;
+      constexpr float sd = s * float(DIR);
+      return make_float2(c * a.x - sd * a.y, c * a.y + sd * a.x);
+    }
+  } else {
+    constexpr float c = TwC<R, k, DIR>::re;
+    constexpr float s = TwC<R, k, DIR>::im;
+    return make_float2(c * a.x - s * a.y, c * a.y + s * a.x);
+  }
+}
+
+// ------------------------------------------------- in-register small DFTs
+
+template <int R>
+struct Split;  // R = P * Q for the composite sizes
+template <> struct Split<8> { static constexpr int P = 4, Q = 2; };
+template <> struct Split<12> { static constexpr int P = 4, Q = 3; };
+template <> struct Split<16> { static constexpr int P = 4, Q = 4; };
+template <> struct Split<20> { static constexpr int P = 4, Q = 5; };
+template <> struct Split<24> { static constexpr int P = 8, Q = 3; };
+template <> struct Split<28> { static constexpr int P = 4, Q = 7; };
+template <> struct Split<32> { static constexpr int P = 8, Q = 4; };
+template <> struct Split<40> { static constexpr int P = 8, Q = 5; };
+template <> struct Split<64> { static constexpr int P = 8, Q = 8; };
+
+template <int R, int DIR>
+struct Dft {
+  // composite: n = Q n1 + n2, k = k1 + P k2
+  static __device__ __forceinline__ void run(float2 (&a)[R]) {
+    constexpr int P = Split<R>::P, Q = Split<R>::Q;
+    float2 Y[Q][P];
+    static_for<0, Q>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      float2 b[P];
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) b[n1] = a[Q * n1 + n2];
+      Dft<P, DIR>::run(b);
+      static_for<0, P>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        Y[n2][k1] = tw_mul<R, n2 * k1, DIR>(b[k1]);
+      });
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      float2 c[Q];
+#pragma unroll
+      for (int n2 = 0; n2 < Q; ++n2) c[n2] = Y[n2][k1];
+      Dft<Q, DIR>::run(c);
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) a[k1 + P * k2] = c[k2];
+    }
+  }
+};
+
+template <int DIR>
+struct Dft<1, DIR> {
+  static __device__ __forceinline__ void run(float2 (&)[1]) {}
+};
+
+template <int DIR>
+struct Dft<2, DIR> {
+  static __device__ __forceinline__ void run(float2 (&a)[2]) {
+    const float2 t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+  }
+};
+
+template <int DIR>
+struct Dft<4, DIR> {
+  static __device__ __forceinline__ void run(float2 (&a)[4]) {
+    const float2 s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+    const float2 s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
+    const float2 j13 = cmul_i(d13, float(DIR));
+    a[0] = cadd(s02, s13);
+    a[2] = csub(s02, s13);
+    a[1] = cadd(d02, j13);
+    a[3] = csub(d02, j13);
+  }
+};
+
+// Odd prime radix by symmetric pairs:
+// X_k = a_0 + sum_n s_n cos(2 pi n k / R) + i DIR sum_n d_n sin(2 pi n k / R)
+// with s_n = a_n + a_{R-n}, d_n = a_n - a_{R-n}; X_{R-k} flips the sine part.
+template <int R, int DIR>
+struct DftOdd {
+  static __device__ __forceinline__ void run(float2 (&a)[R]) {
+    constexpr int H = (R - 1) / 2;
+    float2 s[H], d[H];
+    float2 sum = a[0];
+#pragma unroll
+    for (int n = 1; n <= H; ++n) {
+      s[n - 1] = cadd(a[n], a[R - n]);
+      d[n - 1] = csub(a[n], a[R - n]);
+      sum = cadd(sum, s[n - 1]);
+    }
+    float2 out[R];
+    out[0] = sum;
+    static_for<1, H + 1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      float2 re = a[0], im = make_float2(0.f, 0.f);
+      static_for<1, H + 1>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        constexpr float c = TwC<R, n * k, 1>::re;
+        constexpr float sn = TwC<R, n * k, 1>::im;  // sin(2 pi n k / R)
+        re = make_float2(re.x + c * s[n - 1].x, re.y + c * s[n - 1].y);
+        im = make_float2(im.x + sn * d[n - 1].x, im.y + sn * d[n - 1].y);
+      });
+      const float2 jim = cmul_i(im, float(DIR));
+      out[k] = cadd(re, jim);
+      out[R - k] = csub(re, jim);
+    });
+#pragma unroll
+    for (int k = 0; k < R; ++k) a[k] = out[k];
+  }
+};
+template <int DIR> struct Dft<3, DIR> : DftOdd<3, DIR> {};
+template <int DIR> struct Dft<5, DIR> : DftOdd<5, DIR> {};
+template <int DIR> struct Dft<7, DIR> : DftOdd<7, DIR> {};
+
+// ---------------------------------------------------------------- plans
+
+template <int... Rs>
+struct Radices {};
+
+template <int N>
+struct Plan;
+template <> struct Plan<64> { static constexpr int NT = 8; using R = Radices<8, 8>; };
+template <> struct Plan<128> { static constexpr int NT = 8; using R = Radices<16, 8>; };
+template <> struct Plan<192> { static constexpr int NT = 16; using R = Radices<12, 4, 4>; };
+template <> struct Plan<224> { static constexpr int NT = 8; using R = Radices<28, 4, 2>; };
+template <> struct Plan<256> { static constexpr int NT = 16; using R = Radices<16, 16>; };
+template <> struct Plan<320> { static constexpr int NT = 16; using R = Radices<20, 4, 4>; };
+template <> struct Plan<512> { static constexpr int NT = 32; using R = Radices<16, 16, 2>; };
+template <> struct Plan<1024> { static constexpr int NT = 64; using R = Radices<16, 16, 4>; };
+
+// Offsets of each length's table inside the packed twiddle buffer
+// (tw[k] = exp(-2 pi i k / N), k < N).
+__host__ __device__ constexpr int tw_offset(int N) {
+  return N == 64 ? 0 : N == 128 ? 64 : N == 192 ? 192 : N == 224 ? 384 : N == 256 ? 608
+       : N == 320 ? 864 : N == 512 ? 1184 : N == 1024 ? 1696 : -1;
+}
+constexpr int kTwiddleTotal = 2720;
+constexpr int kSupportedSizes[] = {64, 128, 192, 224, 256, 320, 512, 1024};
+
+// LDS layouts: Lay::addr(idx, seq) gives the slot of element idx of sequence
+// seq.  Column tiles keep T sequences side by side (row-major like global
+// memory); row tiles keep each sequence contiguous with one pad slot per 16.
+template <int T>
+struct ColLay {
+  static __device__ __forceinline__ int addr(int idx, int seq) { return idx * T + seq; }
+};
+template <int N>
+struct RowLay {
+  static constexpr int stride = N + N / 16 + 4;
+  static __device__ __forceinline__ int addr(int idx, int seq) { return seq * stride + idx + (idx >> 4); }
+};
+
+template <int N, int NT, int DIR, int Ns, class Lay, int R, int... Rest>
+__device__ __forceinline__ void fft_stages(float2 (&v)[N / NT], int t, float2* lds, int seq,
+                                           const float2* __restrict__ tw) {
+  constexpr int E = N / NT;
+  constexpr int Q = E / R;
+  static_assert(E % R == 0, "radix must divide the elements per thread");
+  constexpr bool LAST = sizeof...(Rest) == 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int b = t + NT * q;
+    float2 u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[q + r * Q];
+    const int bm = b % Ns;
+    if constexpr (Ns > 1) {
+      constexpr int step = N / (Ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[bm * r * step];
+        if constexpr (DIR > 0) w.y = -w.y;
+        u[r] = cmul(u[r], w);
+      }
+    }
+    Dft<R, DIR>::run(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * Q] = u[r];
+    } else {
+      const int base = (b / Ns) * Ns * R + bm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[Lay::addr(base + r * Ns, seq)] = u[r];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = lds[Lay::addr(t + NT * e, seq)];
+    __syncthreads();
+    fft_stages<N, NT, DIR, Ns * R, Lay, Rest...>(v, t, lds, seq, tw);
+  }
+}
+
+template <int N, int DIR, class Lay, int... Rs>
+__device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[N / Plan<N>::NT], int t, float2* lds,
+                                        int seq, const float2* __restrict__ tw) {
+  fft_stages<N, Plan<N>::NT, DIR, 1, Lay, Rs...>(v, t, lds, seq, tw);
+}
+
+// In-place transform of the cyclic registers.  Every thread of the block must
+// call it (it contains barriers).  `tw` points at this length's table.
+template <int N, int DIR, class Lay>
+__device__ __forceinline__ void fft(float2 (&v)[N / Plan<N>::NT], int t, float2* lds, int seq,
+                                    const float2* __restrict__ tw) {
+  fft_run<N, DIR, Lay>(typename Plan<N>::R{}, v, t, lds, seq, tw);
+}
+
+}  // namespace pics

@@ -1,0 +1,124 @@
+// Internal device-side descriptors and kernel launchers (not part of the ABI).
+#pragma once
+
+#include "common.hpp"
+
+namespace pics {
+
+constexpr int kColT = 16;     // columns per column tile
+constexpr int kRowRR = 16;    // rows per row tile
+constexpr int kPartMax = 64;  // partial sums per slice per reduction
+
+// reduction slots (per slice: kSlots x kPartMax doubles)
+enum PartSlot { P_SIGMA = 0, P_RR = 1, P_BB = 2, P_RHO0 = 3, P_RHO1 = 4, P_AUX = 5, kSlots = 6 };
+
+struct SliceDev {
+  int m, n, nc, mask_kind;  // mask_kind: 0 = line mask uint8[m], 1 = 2D uint8[m][n]
+  int wavelet, levels;      // 0 none, 1 haar, 2 db4
+  float mu, lam, gam;
+  int pad0;
+  long long img;   // element offset of the slice in packed image-shaped buffers
+  long long coil;  // element offset in packed coil-shaped buffers [nc][m][n]
+  long long mask;  // byte offset in the packed mask buffer
+  long long aux;   // offset of the slice's (n / 16) x m FP64 coil-power partials
+};
+
+// Per-slice PCG control block; lives in device memory.
+struct PcgState {
+  int it_a;    // completed x/r updates (written by the update kernel only)
+  int it_r;    // copy of it_a taken by the apply kernel (read by the update kernel)
+  int done;    // 1 once converged, broken down or stopped
+  int status;  // 1 converged, 0 running / max iterations, < 0 error code
+  int iters;   // iterations at exit
+  int maxit;   // per-slice iteration cap for this solve
+  double relres;
+};
+
+// Device pointers shared by the kernels (passed by value).
+struct Ws {
+  const SliceDev* sl;
+  const int* group;       // launch grid.y -> slice index
+  const float2* sens;     // packed [nc][m][n] per slice
+  const uint8_t* mask;    // packed masks
+  const float2* tw;       // packed twiddle tables
+  const float* kinv;      // 1 / (k m n) per pixel (circulant / learned)
+  const float* jac;       // 1 / diag(A) per pixel (Jacobi)
+  double* part;           // [nslices][kSlots][kPartMax]
+  PcgState* st;           // [nslices]
+};
+
+__device__ __forceinline__ double* part_ptr(double* part, int s, int slot) {
+  return part + ((long long)s * kSlots + slot) * kPartMax;
+}
+__device__ __forceinline__ double part_sum(const double* p, int count) {
+  double acc = 0.0;
+  for (int i = 0; i < count; ++i) acc += p[i];
+  return acc;
+}
+
+// preconditioner kinds (same values as the ABI)
+enum { PK_NONE = 0, PK_JACOBI = 1, PK_CIRC = 2, PK_LEARNED = 3 };
+
+// column-tile apply modes
+enum { CA_APPLY = 0, CA_PCG = 1, CA_OUTER = 2 };
+// apply term flags
+enum { TERM_DATA = 1, TERM_TV = 2, TERM_GAMMA = 4, TERM_ALL = 7 };
+// row-tile update modes
+enum { RU_SETUP = 0, RU_UPDATE = 1 };
+
+struct Launch {
+  hipStream_t stream;
+  int m, n;          // common size of the slices in this group
+  int count;         // slices in this group
+  const int* group;  // device array of slice indices
+};
+
+// Arguments of one wavelet pass (see k_sb.hip).
+struct WaveArgs {
+  int level, inverse, pass, last, mode;  // mode 0: store, 1: SB shrink (analysis) / right-hand side (synthesis)
+  const float2* in;
+  float2* out;
+  float2* coef;
+  float2* bw;
+  float2* uw;
+  const float2* g;
+  const float2* ux;
+  const float2* uy;
+  float2* rhs;
+};
+
+struct Simple {
+  hipStream_t stream;
+  int nslices;
+  long long max_pixels;
+};
+
+bool fft_size_supported(int N);
+
+// ---- FFT-path launchers (k_fft_ops.hip)
+hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
+                            const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
+                            float2* g, const float2* g1);
+hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, const float2* b, const float2* q,
+                             float2* x, float2* r, const float2* pn, float2* p, float2* t);
+hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t);
+hipError_t launch_row_z(const Launch& L, const Ws& w, const float2* t, const float2* r, float2* z);
+hipError_t launch_row_fft(const Launch& L, const Ws& w, int inverse, int ncoil_mode, const float2* in, float2* out);
+hipError_t launch_col_fft(const Launch& L, const Ws& w, int inverse, const float2* in, float2* out);
+hipError_t launch_col_sb_init(const Launch& L, const Ws& w, const float2* coil_rows, float2* g1, float2* g,
+                              float2* x);
+hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, float* energy);
+
+// ---- per-pixel kernels (k_sb.hip)
+hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit, const int* maxit_per_slice);
+hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, const float2* x, float2* bx, float2* by, float2* ux,
+                            float2* uy, float2* bw, float2* uw);
+hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, const float2* ux, const float2* uy,
+                                const float2* uw, float2* rhs);
+hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a);
+hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, const float* corr, float* kraw,
+                          float* kinv, float* jac, int* bad);
+hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v);
+
+}  // namespace pics

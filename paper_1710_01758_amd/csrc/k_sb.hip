@@ -1,0 +1,359 @@
+// Per-pixel kernels around the FFT passes: PCG control, the Split Bregman
+// shrink/update steps (Algorithm 1, steps 6-11), the periodised orthonormal
+// wavelet passes and the circulant spectrum assembly.
+//
+// Launch shape: grid (blocks, nslices), a grid-stride loop over one slice's
+// pixels per grid.y, so slices of different sizes share one launch.
+#include "internal.hpp"
+
+namespace pics {
+
+// Lowpass filters.  Haar: 1/sqrt(2) (1, 1).  Daubechies-4 (8 taps, 4 vanishing
+// moments, extremal phase), listed as in Daubechies, Ten Lectures on Wavelets,
+// Table 6.1 (N = 4), normalised to sum sqrt(2).  Highpass g[t] = (-1)^t h[K-1-t].
+__constant__ float c_haar[2] = {0.70710678118654752f, 0.70710678118654752f};
+__constant__ float c_db4[8] = {0.2303778133088964f,  0.7148465705529154f,  0.6308807679298587f,
+                               -0.0279837694168599f, -0.1870348117190931f, 0.0308413818355607f,
+                               0.0328830116668852f,  -0.0105974017850690f};
+
+__device__ __forceinline__ float2 shrink(float2 v, float thr) {
+  const float a = sqrtf(v.x * v.x + v.y * v.y);
+  if (!(a > thr)) return make_float2(0.f, 0.f);
+  const float s = 1.0f - thr / a;
+  return make_float2(v.x * s, v.y * s);
+}
+
+// ------------------------------------------------------------ PCG control
+
+__global__ void k_pcg_reset(Ws w, int nslices, int maxit, const int* __restrict__ maxit_per_slice) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslices) return;
+  PcgState st;
+  st.it_a = 0;
+  st.it_r = 0;
+  st.done = 0;
+  st.status = 0;
+  st.iters = 0;
+  st.maxit = maxit_per_slice ? maxit_per_slice[s] : maxit;
+  st.relres = 0.0;
+  w.st[s] = st;
+}
+
+// Stop test at the set-up and at host polling points.  A zero right-hand side
+// gives x = 0 with no iterations.
+__global__ __launch_bounds__(256) void k_pcg_check(Ws w, double tol, int setup, float2* __restrict__ x) {
+  const int s = blockIdx.x;
+  const SliceDev sd = w.sl[s];
+  PcgState* st = w.st + s;
+  __shared__ int zero_x;
+  if (threadIdx.x == 0) {
+    zero_x = 0;
+    if (!st->done) {
+      const int nrt = sd.m / kRowRR;
+      const double rr = part_sum(part_ptr(w.part, s, P_RR), nrt);
+      const double bb = part_sum(part_ptr(w.part, s, P_BB), nrt);
+      int status = -100;
+      if (setup && bb == 0.0) {
+        zero_x = 1;
+        status = 1;
+      } else if (rr <= tol * tol * bb) {
+        status = 1;
+      } else if (st->it_a >= st->maxit) {
+        status = 0;
+      }
+      if (status != -100) {
+        st->done = 1;
+        st->status = status;
+        st->iters = st->it_a;
+        st->relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  if (zero_x) {
+    const long long np = (long long)sd.m * sd.n;
+    for (long long p = threadIdx.x; p < np; p += blockDim.x) x[sd.img + p] = make_float2(0.f, 0.f);
+  }
+}
+
+// ------------------------------------------------------- TV shrink/update
+// D_x x = x[i,j] - x[i-1,j], D_y x = x[i,j] - x[i,j-1] (periodic);
+// v = D x + b;  d = shrink(v, 1/lam);  b <- v - d;  u = d - b (the next
+// right-hand side uses D^H u).  With no wavelet the same is done on x itself
+// with threshold 1/gam.
+__global__ __launch_bounds__(256) void k_tv_shrink(Ws w, const float2* __restrict__ x, float2* __restrict__ bx,
+                                                   float2* __restrict__ by, float2* __restrict__ ux,
+                                                   float2* __restrict__ uy, float2* __restrict__ bw,
+                                                   float2* __restrict__ uw) {
+  const int s = blockIdx.y;
+  const SliceDev sd = w.sl[s];
+  const int m = sd.m, n = sd.n;
+  const long long np = (long long)m * n;
+  const float tl = 1.0f / sd.lam, tg = 1.0f / sd.gam;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += (long long)gridDim.x * blockDim.x) {
+    const int i = int(p / n), j = int(p % n);
+    const long long o = sd.img;
+    const float2 xc = x[o + p];
+    const float2 xu = x[o + (long long)((i - 1 + m) % m) * n + j];
+    const float2 xl = x[o + (long long)i * n + (j - 1 + n) % n];
+    {
+      const float2 v = cadd(csub(xc, xu), bx[o + p]);
+      const float2 d = shrink(v, tl);
+      const float2 b = csub(v, d);
+      bx[o + p] = b;
+      ux[o + p] = csub(d, b);
+    }
+    {
+      const float2 v = cadd(csub(xc, xl), by[o + p]);
+      const float2 d = shrink(v, tl);
+      const float2 b = csub(v, d);
+      by[o + p] = b;
+      uy[o + p] = csub(d, b);
+    }
+    if (sd.levels == 0 || sd.wavelet == 0) {
+      const float2 v = cadd(xc, bw[o + p]);
+      const float2 d = shrink(v, tg);
+      const float2 b = csub(v, d);
+      bw[o + p] = b;
+      uw[o + p] = csub(d, b);
+    }
+  }
+}
+
+// right-hand side g + lam (D_x^H u_x + D_y^H u_y) + gam * wv at pixel (i, j)
+__device__ __forceinline__ float2 rhs_at(const SliceDev& sd, long long o, int i, int j, const float2* g,
+                                         const float2* ux, const float2* uy, float2 wv) {
+  const int m = sd.m, n = sd.n;
+  const long long p = (long long)i * n + j;
+  const float2 a = csub(ux[o + p], ux[o + (long long)((i + 1) % m) * n + j]);
+  const float2 b = csub(uy[o + p], uy[o + (long long)i * n + (j + 1) % n]);
+  const float2 gv = g[o + p];
+  return make_float2(gv.x + sd.lam * (a.x + b.x) + sd.gam * wv.x, gv.y + sd.lam * (a.y + b.y) + sd.gam * wv.y);
+}
+
+__global__ __launch_bounds__(256) void k_rhs_nowavelet(Ws w, const float2* __restrict__ g,
+                                                       const float2* __restrict__ ux, const float2* __restrict__ uy,
+                                                       const float2* __restrict__ uw, float2* __restrict__ rhs) {
+  const int s = blockIdx.y;
+  const SliceDev sd = w.sl[s];
+  const long long np = (long long)sd.m * sd.n;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += (long long)gridDim.x * blockDim.x) {
+    const int i = int(p / sd.n), j = int(p % sd.n);
+    rhs[sd.img + p] = rhs_at(sd, sd.img, i, j, g, ux, uy, uw[sd.img + p]);
+  }
+}
+
+// ---------------------------------------------------------------- wavelets
+// Level l acts on the top-left (m >> l) x (n >> l) block (row stride n).
+// Analysis, pass 0 (along axis 1):  tmp[i][k] = sum_t h[t] in[i][(2k+t) mod nl],
+//                                   tmp[i][nl/2 + k] = sum_t g[t] in[...]
+// Analysis, pass 1 (along axis 0):  coefficient rows k and ml/2 + k; the
+// approximation block goes to `llout` unless this is the last level, every
+// other coefficient is final and is either stored (`coef`) or consumed by the
+// shrink/update of Algorithm 1 steps 8 and 11 (bw, uw).
+// Synthesis is the transpose: pass 0 along axis 0, pass 1 along axis 1; the
+// finest level's pass 1 can emit the right-hand side directly.
+
+
+__device__ __forceinline__ int filt_len(int wavelet) { return wavelet == 1 ? 2 : 8; }
+__device__ __forceinline__ float filt_h(int wavelet, int t) { return wavelet == 1 ? c_haar[t] : c_db4[t]; }
+__device__ __forceinline__ float filt_g(int wavelet, int t) {
+  const int K = filt_len(wavelet);
+  const float v = filt_h(wavelet, K - 1 - t);
+  return (t & 1) ? -v : v;
+}
+
+__device__ __forceinline__ void coef_out(const SliceDev& sd, const WaveArgs& a, long long pos, float2 c) {
+  if (a.mode == 0) {
+    a.coef[pos] = c;
+  } else {
+    const float2 v = cadd(c, a.bw[pos]);
+    const float2 d = shrink(v, 1.0f / sd.gam);
+    const float2 b = csub(v, d);
+    a.bw[pos] = b;
+    a.uw[pos] = csub(d, b);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_wavelet(Ws w, WaveArgs a) {
+  const int s = blockIdx.y;
+  const SliceDev sd = w.sl[s];
+  if (sd.wavelet == 0 || a.level >= sd.levels) return;
+  const int n = sd.n;
+  const int ml = sd.m >> a.level, nl = n >> a.level;
+  const int mh = ml / 2, nh = nl / 2;
+  const int K = filt_len(sd.wavelet);
+  const long long o = sd.img;
+  const bool lastlev = (a.level == sd.levels - 1);
+  long long items;
+  if (!a.inverse) items = a.pass == 0 ? (long long)ml * nh : (long long)mh * nl;
+  else items = (long long)ml * nl;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < items;
+       p += (long long)gridDim.x * blockDim.x) {
+    if (!a.inverse && a.pass == 0) {
+      const int i = int(p / nh), k = int(p % nh);
+      float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+      for (int t = 0; t < K; ++t) {
+        const float2 v = a.in[o + (long long)i * n + (2 * k + t) % nl];
+        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+        lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
+        hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
+      }
+      a.out[o + (long long)i * n + k] = lo;
+      a.out[o + (long long)i * n + nh + k] = hi;
+    } else if (!a.inverse) {
+      const int k = int(p / nl), j = int(p % nl);
+      float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+      for (int t = 0; t < K; ++t) {
+        const float2 v = a.in[o + (long long)((2 * k + t) % ml) * n + j];
+        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+        lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
+        hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
+      }
+      const long long plo = o + (long long)k * n + j, phi = o + (long long)(mh + k) * n + j;
+      if (j < nh && !lastlev) a.out[plo] = lo;  // approximation block for the next level
+      else coef_out(sd, a, plo, lo);
+      coef_out(sd, a, phi, hi);
+    } else if (a.pass == 0) {
+      // synthesis along axis 0: out[i][j] from rows [0, mh) (low) and [mh, ml) (high)
+      const int i = int(p / nl), j = int(p % nl);
+      const float2* lowsrc = (j < nh && !lastlev) ? a.in : a.coef;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int t = (i & 1); t < K; t += 2) {
+        const int k = (((i - t) % ml + ml) % ml) / 2;
+        const float2 lv = lowsrc[o + (long long)k * n + j];
+        const float2 hv = a.coef[o + (long long)(mh + k) * n + j];
+        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+        acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
+      }
+      a.out[o + (long long)i * n + j] = acc;
+    } else {
+      // synthesis along axis 1 from tmp columns [0, nh) and [nh, nl)
+      const int i = int(p / nl), jj = int(p % nl);
+      float2 acc = make_float2(0.f, 0.f);
+      for (int t = (jj & 1); t < K; t += 2) {
+        const int k = (((jj - t) % nl + nl) % nl) / 2;
+        const float2 lv = a.in[o + (long long)i * n + k];
+        const float2 hv = a.in[o + (long long)i * n + nh + k];
+        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+        acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
+      }
+      if (a.level == 0 && a.mode == 1) {
+        a.rhs[o + (long long)i * n + jj] = rhs_at(sd, o, i, jj, a.g, a.ux, a.uy, acc);
+      } else {
+        a.out[o + (long long)i * n + jj] = acc;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------ spectrum assembly
+// k(u, v) = mu k_c(u) + lam (4 - 2 cos(2 pi u / m) - 2 cos(2 pi v / n)) + gam
+// for a line mask, k_c(u) = (1/N^2) sum_l r(l) Pbar(l - u); optional
+// multiplicative correction; outputs k, 1 / (k m n) and the Jacobi inverse
+// diagonal 1 / (mu |Omega|/N sum_c |S_c|^2 + 4 lam + gam).
+__global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict__ pbar, const float* __restrict__ corr,
+                                                 float* __restrict__ kraw, float* __restrict__ kinv,
+                                                 float* __restrict__ jac, int* __restrict__ bad) {
+  __shared__ double sp[1024];
+  __shared__ double skc[1024];
+  __shared__ int ssum;
+  const int s = blockIdx.y;
+  const SliceDev sd = w.sl[s];
+  const int m = sd.m, n = sd.n;
+  const int ntile = n / kColT;
+  const uint8_t* mk = w.mask + sd.mask;
+  if (threadIdx.x == 0) ssum = 0;
+  __syncthreads();
+  int cnt = 0;
+  for (int u = threadIdx.x; u < m; u += blockDim.x) {
+    double a = 0.0;
+    for (int tl = 0; tl < ntile; ++tl) a += pbar[sd.aux + (long long)tl * m + u];
+    sp[u] = a * n;
+    cnt += mk[u] ? 1 : 0;
+  }
+  atomicAdd(&ssum, cnt);
+  __syncthreads();
+  const double N = (double)m * n;
+  for (int u = threadIdx.x; u < m; u += blockDim.x) {
+    double a = 0.0;
+    for (int l = 0; l < m; ++l)
+      if (mk[l]) a += sp[(l - u + m) % m];
+    skc[u] = a / (N * N);
+  }
+  __syncthreads();
+  const double frac = (double)ssum / m;
+  const long long np = (long long)m * n;
+  int badl = 0;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += (long long)gridDim.x * blockDim.x) {
+    const int u = int(p / n), v = int(p % n);
+    double k = (double)sd.mu * skc[u] +
+               (double)sd.lam * (4.0 - 2.0 * cospi(2.0 * u / m) - 2.0 * cospi(2.0 * v / n)) + (double)sd.gam;
+    if (corr) k *= (double)corr[sd.img + p];
+    if (!(k > 0.0) || !isfinite(k)) badl = 1;
+    kraw[sd.img + p] = (float)k;
+    kinv[sd.img + p] = (float)(1.0 / (k * N));
+    const double dA = (double)sd.mu * frac * (double)jac[sd.img + p] + 4.0 * sd.lam + sd.gam;
+    jac[sd.img + p] = (float)(1.0 / dA);
+  }
+  if (badl) atomicOr(bad, 1);
+}
+
+__global__ void k_fill(float2* p, long long count, float2 v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ============================================================== launchers
+
+static dim3 simple_grid(const Simple& S) {
+  long long blocks = (S.max_pixels + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  return dim3((unsigned)blocks, S.nslices);
+}
+
+hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit, const int* maxit_per_slice) {
+  hipLaunchKernelGGL(k_pcg_reset, dim3((nslices + 63) / 64), dim3(64), 0, st, w, nslices, maxit, maxit_per_slice);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(nslices), dim3(256), 0, st, w, tol, setup, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, const float2* x, float2* bx, float2* by, float2* ux,
+                            float2* uy, float2* bw, float2* uw) {
+  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, x, bx, by, ux, uy, bw, uw);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, const float2* ux, const float2* uy,
+                                const float2* uw, float2* rhs) {
+  hipLaunchKernelGGL(k_rhs_nowavelet, simple_grid(S), dim3(256), 0, S.stream, w, g, ux, uy, uw, rhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a) {
+  hipLaunchKernelGGL(k_wavelet, simple_grid(S), dim3(256), 0, S.stream, w, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, const float* corr, float* kraw,
+                          float* kinv, float* jac, int* bad) {
+  dim3 grid = simple_grid(S);
+  if (grid.x > 64) grid.x = 64;
+  hipLaunchKernelGGL(k_build_k, grid, dim3(256), 0, S.stream, w, pbar, corr, kraw, kinv, jac, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v) {
+  long long blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
+  return hipGetLastError();
+}
+
+}  // namespace pics
