@@ -24,6 +24,7 @@ struct pics_ctx {
   long long img_total = 0, coil_total = 0, mask_total = 0, aux_total = 0, max_pixels = 0;
   int max_levels = 0;
   bool any_wavelet = false, any_nowavelet = false;
+  std::vector<int> wave_tiles;  // per level: max over slices of 16 x 16 coefficient tiles
 
   struct Group {
     int m, n;
@@ -122,6 +123,59 @@ bool levels_ok(int m, int n, int levels) {
 }
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+// W (all levels).  Level l reads `in` (l = 0) or the approximation block the
+// previous level left in the ping-pong buffers, and writes its own
+// approximation block to w1 (l even) or w2 (l odd); final coefficients go to
+// `coef` (mode 0) or through the shrink/update into bw / uw (mode 1).
+int wavelet_analysis(pics_ctx* c, const float2* in, int mode, float2* coef, float2* bw, float2* uw, const TvArgs& tv) {
+  const Ws w = make_ws(c);
+  const Simple S = make_simple(c);
+  for (int l = 0; l < c->max_levels; ++l) {
+    WaveArgs a{};
+    a.level = l;
+    a.inverse = 0;
+    a.mode = mode;
+    a.in = l == 0 ? in : ((l - 1) % 2 == 0 ? c->w1 : c->w2);
+    a.out = l % 2 == 0 ? c->w1 : c->w2;
+    a.coef = coef;
+    a.bw = bw;
+    a.uw = uw;
+    TvArgs t = tv;
+    t.enabled = (l == 0) ? tv.enabled : 0;
+    const hipError_t e = launch_wavelet(S, w, a, t, c->wave_tiles[l]);
+    if (e != hipSuccess) return fail(c, PICS_ERR_HIP, "wavelet analysis: %s", hipGetErrorString(e));
+  }
+  return PICS_OK;
+}
+
+// W^H (all levels), coarsest first.  Mode 0 writes the image to `out`;
+// mode 1 writes the Split Bregman right-hand side g + lam (D_x^H u_x +
+// D_y^H u_y) + gam W^H coef into rhs.
+int wavelet_synthesis(pics_ctx* c, const float2* coef, int mode, float2* out, const float2* g, const float2* ux,
+                      const float2* uy, float2* rhs) {
+  const Ws w = make_ws(c);
+  const Simple S = make_simple(c);
+  const int L = c->max_levels;
+  auto buf = [&](int l) { return ((L - 1 - l) % 2 == 0) ? c->w1 : c->w2; };
+  for (int l = L - 1; l >= 0; --l) {
+    WaveArgs a{};
+    a.level = l;
+    a.inverse = 1;
+    a.mode = mode;
+    a.in = l + 1 < L ? buf(l + 1) : nullptr;
+    a.out = l == 0 ? out : buf(l);
+    a.coef = const_cast<float2*>(coef);
+    a.g = g;
+    a.ux = ux;
+    a.uy = uy;
+    a.rhs = rhs;
+    TvArgs t{};
+    const hipError_t e = launch_wavelet(S, w, a, t, c->wave_tiles[l]);
+    if (e != hipSuccess) return fail(c, PICS_ERR_HIP, "wavelet synthesis: %s", hipGetErrorString(e));
+  }
+  return PICS_OK;
+}
 
 }  // namespace
 
@@ -223,6 +277,11 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
       c->groups[it->second].idx.push_back(s);
     }
   }
+
+  c->wave_tiles.assign(c->max_levels, 0);
+  for (int l = 0; l < c->max_levels; ++l)
+    for (const SliceDev& sd : c->sl)
+      if (sd.levels > l) c->wave_tiles[l] = std::max(c->wave_tiles[l], wavelet_tiles(sd.m, sd.n, l));
 
   // ---- one allocation for everything
   const long long I = c->img_total;
@@ -372,38 +431,9 @@ int pics_wavelet(pics_ctx* c, const void* in, void* out, int32_t inverse) {
       HIPCHK(c, hipMemcpyAsync((float2*)out + c->sl[s].img, (const float2*)in + c->sl[s].img,
                                sizeof(float2) * c->sl[s].m * c->sl[s].n, hipMemcpyDeviceToDevice, c->stream));
   }
-  WaveArgs a{};
-  a.mode = 0;
-  if (!inverse) {
-    for (int l = 0; l < c->max_levels; ++l) {
-      a.level = l;
-      a.inverse = 0;
-      a.pass = 0;
-      a.in = l == 0 ? (const float2*)in : c->w1;
-      a.out = c->w2;
-      HIPCHK(c, launch_wavelet(S, w, a));
-      a.pass = 1;
-      a.in = c->w2;
-      a.out = c->w1;
-      a.coef = (float2*)out;
-      HIPCHK(c, launch_wavelet(S, w, a));
-    }
-  } else {
-    for (int l = c->max_levels - 1; l >= 0; --l) {
-      a.level = l;
-      a.inverse = 1;
-      a.pass = 0;
-      a.in = c->w1;
-      a.coef = (float2*)in;
-      a.out = c->w2;
-      HIPCHK(c, launch_wavelet(S, w, a));
-      a.pass = 1;
-      a.in = c->w2;
-      a.out = l == 0 ? (float2*)out : c->w1;
-      HIPCHK(c, launch_wavelet(S, w, a));
-    }
-  }
-  return PICS_OK;
+  TvArgs none{};
+  if (!inverse) return wavelet_analysis(c, (const float2*)in, 0, (float2*)out, nullptr, nullptr, none);
+  return wavelet_synthesis(c, (const float2*)in, 0, (float2*)out, nullptr, nullptr, nullptr, nullptr);
 }
 
 }  // extern "C"
@@ -433,18 +463,24 @@ int pcg_run(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, cons
     for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
   }
   const float2* zsrc = circ ? c->z : c->r;
+  // search directions alternate between two buffers: iteration k reads
+  // p_k from pbuf[k & 1] and writes p_{k+1} to pbuf[(k + 1) & 1]
+  float2* pbuf[2] = {c->p, c->pn};
   int done_iters = 0;
   int chunk = std::max(1, c->poll_chunk);
   if (maxit_dev) chunk = std::max(1, maxit_max);  // iteration-locked: one poll at the end
   while (true) {
     const int todo = std::min(chunk, maxit_max - done_iters);
     for (int k = 0; k < todo; ++k) {
+      const int kk = done_iters + k;
+      float2* pold = pbuf[kk & 1];
+      float2* pnew = pbuf[(kk + 1) & 1];
       for (auto& g : c->groups)
-        HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, c->p,
-                                   c->pn, c->q, nullptr, nullptr));
+        HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, pold,
+                                   pnew, c->q, nullptr, nullptr));
       for (auto& g : c->groups)
-        HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, c->pn,
-                                    c->p, c->t));
+        HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, pnew,
+                                    nullptr, c->t));
       if (circ) {
         for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
         for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
@@ -549,25 +585,8 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
       // step 4: b = g_j + lam [D_x^H (d_x - b_x) + D_y^H (d_y - b_y)] + gam W^H (d_w - b_w)
       if (c->any_nowavelet) HIPCHK(c, launch_rhs_nowavelet(S, w, c->g, c->ux, c->uy, c->uw, c->rhs));
       if (c->any_wavelet) {
-        WaveArgs a{};
-        a.mode = 1;
-        a.g = c->g;
-        a.ux = c->ux;
-        a.uy = c->uy;
-        a.rhs = c->rhs;
-        for (int l = c->max_levels - 1; l >= 0; --l) {
-          a.level = l;
-          a.inverse = 1;
-          a.pass = 0;
-          a.in = c->w1;
-          a.coef = c->uw;
-          a.out = c->w2;
-          HIPCHK(c, launch_wavelet(S, w, a));
-          a.pass = 1;
-          a.in = c->w2;
-          a.out = c->w1;
-          HIPCHK(c, launch_wavelet(S, w, a));
-        }
+        const int rc = wavelet_synthesis(c, c->uw, 1, nullptr, c->g, c->ux, c->uy, c->rhs);
+        if (rc) return rc;
       }
       // step 5: PCG warm-started at x
       int rc;
@@ -583,24 +602,11 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
       if (pcg_iters)
         for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
       // steps 6-11: TV and wavelet shrink / Bregman updates
-      HIPCHK(c, launch_tv_shrink(S, w, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+      if (c->any_nowavelet) HIPCHK(c, launch_tv_shrink(S, w, 1, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
       if (c->any_wavelet) {
-        WaveArgs a{};
-        a.mode = 1;
-        a.bw = c->bw;
-        a.uw = c->uw;
-        for (int l = 0; l < c->max_levels; ++l) {
-          a.level = l;
-          a.inverse = 0;
-          a.pass = 0;
-          a.in = l == 0 ? x : c->w1;
-          a.out = c->w2;
-          HIPCHK(c, launch_wavelet(S, w, a));
-          a.pass = 1;
-          a.in = c->w2;
-          a.out = c->w1;
-          HIPCHK(c, launch_wavelet(S, w, a));
-        }
+        TvArgs tv{1, c->bx, c->by, c->ux, c->uy};
+        const int rc = wavelet_analysis(c, x, 1, nullptr, c->bw, c->uw, tv);
+        if (rc) return rc;
       }
       q_valid = false;
     }

@@ -87,6 +87,15 @@ struct WaveArgs {
   float2* rhs;
 };
 
+// Fused TV shrink/update carried by the level-0 wavelet analysis.
+struct TvArgs {
+  int enabled;
+  float2* bx;
+  float2* by;
+  float2* ux;
+  float2* uy;
+};
+
 struct Simple {
   hipStream_t stream;
   int nslices;
@@ -112,11 +121,14 @@ hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, flo
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit, const int* maxit_per_slice);
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
-hipError_t launch_tv_shrink(const Simple& S, const Ws& w, const float2* x, float2* bx, float2* by, float2* ux,
-                            float2* uy, float2* bw, float2* uw);
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const float2* x, float2* bx,
+                            float2* by, float2* ux, float2* uy, float2* bw, float2* uw);
 hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, const float2* ux, const float2* uy,
                                 const float2* uw, float2* rhs);
-hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a);
+// one wavelet level (analysis or synthesis per a.inverse); `tiles` = max over
+// slices of the level's 16 x 16 coefficient tiles
+hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a, const TvArgs& tv, int tiles);
+int wavelet_tiles(int m, int n, int level);
 hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, const float* corr, float* kraw,
                           float* kinv, float* jac, int* bad);
 hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v);

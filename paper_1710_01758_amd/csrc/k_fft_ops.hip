@@ -57,25 +57,36 @@ __device__ __forceinline__ void pcg_mark_done(const Ws& w, int s, int status, do
   st->relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
 }
 
+// Copy this length's twiddle table into LDS so that the FFT stages read it
+// with LDS instructions (the global-load counter then only tracks data).
+template <int N, int TH>
+__device__ __forceinline__ void stage_twiddles(float2* s_tw, const float2* __restrict__ tw_global) {
+  const float2* __restrict__ src = tw_global + tw_offset(N);
+  for (int k = threadIdx.x; k < N; k += TH) s_tw[k] = src[k];
+}
+
 // ----------------------------------------------------------------------------
 // System operator with a line mask, one column tile per workgroup:
 //   out = mu sum_c conj(S_c) F_m^H diag(r) F_m (S_c p) + lam (D_x^H D_x + D_y^H D_y) p + gam p
 // (Eq. system with W^H W = I).  A line mask samples whole k-space rows, so
 // F^H R F factors into a length-m transform along axis 0 only; the 1/m of the
-// unitary pair is folded into the mask.
-// Modes: CA_APPLY  p = xin
-//        CA_PCG    p = zs + beta p_old (beta from the rho partials), written to pn;
-//                  sigma = Re(p^H A p) partial
-//        CA_OUTER  p = xin; also g <- g + g1 - (data term)
+// unitary pair is folded into the mask.  The coil maps of coil c + 1 are
+// loaded while coil c is transformed.
+// MODE CA_APPLY  p = xin
+//      CA_PCG    p = zs + beta p_old (beta from the rho partials), written to pn;
+//                sigma = Re(p^H A p) partial
+//      CA_OUTER  p = xin; also g <- g + g1 - (data term)
 // ----------------------------------------------------------------------------
-template <int M>
+template <int M, int MODE>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
-    Ws w, int mode, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
+    Ws w, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
     const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, float2* __restrict__ g,
     const float2* __restrict__ g1) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT, TH = ColCfg<M>::THREADS;
   constexpr int TS = T + 2;  // tile stride with the two halo columns
+  constexpr int HP = (2 * M + TH - 1) / TH;
   __shared__ float2 lds[M * TS];
+  __shared__ float2 s_tw[M];
   __shared__ double red[16];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -83,12 +94,12 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int j0 = blockIdx.x * T;
   const int col = j0 + j;
-  const long long base = sd.img;
+  const float2* __restrict__ xs = xin + sd.img;
 
   int it = 0;
   float beta = 0.f;
   bool first = true;
-  if (mode == CA_PCG) {
+  if (MODE == CA_PCG) {
     PcgState* st = w.st + s;
     if (st->done) return;
     int status;
@@ -105,101 +116,144 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
       beta = float(rho_i / rho_p);
     }
   }
+  stage_twiddles<M, TH>(s_tw, w.tw);
 
-  auto pval = [&](long long idx) -> float2 {
-    if (mode != CA_PCG) return xin[idx];
-    float2 zs;
-    if (pk == PK_NONE) {
-      zs = zsrc[idx];
-    } else if (pk == PK_JACOBI) {
-      zs = cscale(zsrc[idx], w.jac[idx]);
-    } else {
-      zs = zsrc[idx];
-    }
-    if (first) return zs;
-    const float2 po = pold[idx];
-    return make_float2(zs.x + beta * po.x, zs.y + beta * po.y);
-  };
-
-  float2 pv[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = t + NT * e;
-    const long long idx = base + (long long)i * n + col;
-    pv[e] = pval(idx);
-    lds[i * TS + j + 1] = pv[e];
-    if (mode == CA_PCG) pn[idx] = pv[e];
-  }
+  // p for the tile (cyclic rows) and the two halo columns, loads batched
   const int jl = (j0 - 1 + n) % n, jr = (j0 + T) % n;
-  for (int h = threadIdx.x; h < 2 * M; h += TH) {
+  int hoff[HP];
+#pragma unroll
+  for (int k = 0; k < HP; ++k) {
+    const int h = threadIdx.x + k * TH;
     const int side = h / M, i = h % M;
-    const int jh = side ? jr : jl;
-    lds[i * TS + (side ? T + 1 : 0)] = pval(base + (long long)i * n + jh);
+    hoff[k] = h < 2 * M ? i * n + (side ? jr : jl) : 0;
   }
-  __syncthreads();
-  // q starts as the diagonal-in-Fourier terms lam (D_x^H D_x + D_y^H D_y) p + gam p
-  float2 q[E];
-  const float mu = sd.mu, lam = sd.lam, gam = sd.gam;
+  float2 pv[E], ph[HP];
+  if (MODE != CA_PCG) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = t + NT * e;
-    float2 a = make_float2(0.f, 0.f);
-    if (terms & TERM_TV) {
-      const int iu = (i - 1 + M) % M, id = (i + 1) % M;
-      const float2 c = lds[i * TS + j + 1];
-      const float2 u = lds[iu * TS + j + 1], d = lds[id * TS + j + 1];
-      const float2 l = lds[i * TS + j], r = lds[i * TS + j + 2];
-      a = make_float2(lam * (4.f * c.x - u.x - d.x - l.x - r.x), lam * (4.f * c.y - u.y - d.y - l.y - r.y));
+    for (int e = 0; e < E; ++e) pv[e] = xs[(t + NT * e) * n + col];
+#pragma unroll
+    for (int k = 0; k < HP; ++k) ph[k] = xs[hoff[k]];
+  } else {
+    const float2* __restrict__ zs = zsrc + sd.img;
+    const float2* __restrict__ po = pold + sd.img;
+    const float* __restrict__ jc = w.jac + sd.img;
+#pragma unroll
+    for (int e = 0; e < E; ++e) pv[e] = zs[(t + NT * e) * n + col];
+#pragma unroll
+    for (int k = 0; k < HP; ++k) ph[k] = zs[hoff[k]];
+    if (pk == PK_JACOBI) {
+      float jv[E], jh[HP];
+#pragma unroll
+      for (int e = 0; e < E; ++e) jv[e] = jc[(t + NT * e) * n + col];
+#pragma unroll
+      for (int k = 0; k < HP; ++k) jh[k] = jc[hoff[k]];
+#pragma unroll
+      for (int e = 0; e < E; ++e) pv[e] = cscale(pv[e], jv[e]);
+#pragma unroll
+      for (int k = 0; k < HP; ++k) ph[k] = cscale(ph[k], jh[k]);
     }
-    if (terms & TERM_GAMMA) a = make_float2(a.x + gam * pv[e].x, a.y + gam * pv[e].y);
-    q[e] = a;
-  }
-  __syncthreads();
-
-  // data term, accumulated coil by coil: mu conj(S_c) F^H R F (S_c p)
-  float2 dat[E];
+    if (!first) {
+      float2 ov[E], oh[HP];
 #pragma unroll
-  for (int e = 0; e < E; ++e) dat[e] = make_float2(0.f, 0.f);
-  if (terms & TERM_DATA) {
+      for (int e = 0; e < E; ++e) ov[e] = po[(t + NT * e) * n + col];
+#pragma unroll
+      for (int k = 0; k < HP; ++k) oh[k] = po[hoff[k]];
+#pragma unroll
+      for (int e = 0; e < E; ++e) pv[e] = make_float2(pv[e].x + beta * ov[e].x, pv[e].y + beta * ov[e].y);
+#pragma unroll
+      for (int k = 0; k < HP; ++k) ph[k] = make_float2(ph[k].x + beta * oh[k].x, ph[k].y + beta * oh[k].y);
+    }
+    float2* __restrict__ pno = pn + sd.img;
+#pragma unroll
+    for (int e = 0; e < E; ++e) pno[(t + NT * e) * n + col] = pv[e];
+  }
+  // data term sum_c conj(S_c) F^H R F (S_c p), coil maps of c + 1 in flight
+  float2 acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
+  if ((terms & TERM_DATA) && sd.nc > 0) {
     const uint8_t* mk = w.mask + sd.mask;
     unsigned mbits = 0u;  // bit e: frequency row t + NT e sampled
 #pragma unroll
     for (int e = 0; e < E; ++e) mbits |= (mk[t + NT * e] ? 1u : 0u) << e;
     const float inv_m = 1.0f / M;
-    const float2* __restrict__ tw = w.tw + tw_offset(M);
-    const float2* S = w.sens + sd.coil;
-    for (int c = 0; c < sd.nc; ++c) {
-      const float2* Sc = S + (long long)c * M * n;
-      float2 sv[E], v[E];
+    const float2* __restrict__ S = w.sens + sd.coil + t * n + col;
+    const int plane = M * n;
+    float2 sv[E], sn[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int i = t + NT * e;
-        sv[e] = Sc[(long long)i * n + col];
-        v[e] = cmul(sv[e], pv[e]);
+    for (int e = 0; e < E; ++e) sv[e] = S[NT * e * n];
+    for (int c = 0; c < sd.nc; ++c) {
+      if (c + 1 < sd.nc) {
+        const float2* __restrict__ Sn = S + (long long)(c + 1) * plane;
+#pragma unroll
+        for (int e = 0; e < E; ++e) sn[e] = Sn[NT * e * n];
       }
-      fft<M, -1, ColLay<T>>(v, t, lds, j, tw);
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cmul(sv[e], pv[e]);
+      fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ((mbits >> e) & 1u) ? inv_m : 0.f);
-      fft<M, +1, ColLay<T>>(v, t, lds, j, tw);
+      fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
-      for (int e = 0; e < E; ++e) dat[e] = cadd(dat[e], cconjmul(sv[e], v[e]));
+      for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(sv[e], v[e]));
+#pragma unroll
+      for (int e = 0; e < E; ++e) sv[e] = sn[e];
     }
   }
+  __syncthreads();  // the FFTs are done with the LDS buffer
 
-  double sig = 0.0;
+  // Fourier-diagonal terms lam (D_x^H D_x + D_y^H D_y) p + gam p on the tile
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[(t + NT * e) * TS + j + 1] = pv[e];
+#pragma unroll
+  for (int k = 0; k < HP; ++k) {
+    const int h = threadIdx.x + k * TH;
+    if (h < 2 * M) lds[(h % M) * TS + (h / M ? T + 1 : 0)] = ph[k];
+  }
+  __syncthreads();
+  const float mu = sd.mu, lam = sd.lam, gam = sd.gam;
+  float2 q[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i = t + NT * e;
-    const long long idx = base + (long long)i * n + col;
-    const float2 qv = make_float2(q[e].x + mu * dat[e].x, q[e].y + mu * dat[e].y);
-    out[idx] = qv;
-    sig += (double)pv[e].x * (double)qv.x + (double)pv[e].y * (double)qv.y;
-    if (mode == CA_OUTER) {
-      const float2 gv = g[idx], g1v = g1[idx];
-      g[idx] = make_float2(gv.x + g1v.x - mu * dat[e].x, gv.y + g1v.y - mu * dat[e].y);
+    float2 a = make_float2(mu * acc[e].x, mu * acc[e].y);
+    if (terms & TERM_TV) {
+      const int iu = (i - 1 + M) % M, id = (i + 1) % M;
+      const float2 c = lds[i * TS + j + 1];
+      const float2 u = lds[iu * TS + j + 1], d = lds[id * TS + j + 1];
+      const float2 l = lds[i * TS + j], r = lds[i * TS + j + 2];
+      a = make_float2(a.x + lam * (4.f * c.x - u.x - d.x - l.x - r.x), a.y + lam * (4.f * c.y - u.y - d.y - l.y - r.y));
+    }
+    if (terms & TERM_GAMMA) a = make_float2(a.x + gam * pv[e].x, a.y + gam * pv[e].y);
+    q[e] = a;
+  }
+
+  float2* __restrict__ o = out + sd.img;
+  double sig = 0.0;
+  if (MODE == CA_OUTER) {
+    float2* __restrict__ gg = g + sd.img;
+    const float2* __restrict__ g1s = g1 + sd.img;
+    float2 gv[E], g1v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      gv[e] = gg[(t + NT * e) * n + col];
+      g1v[e] = g1s[(t + NT * e) * n + col];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int off = (t + NT * e) * n + col;
+      o[off] = q[e];
+      gg[off] = make_float2(gv[e].x + g1v[e].x - mu * acc[e].x, gv[e].y + g1v[e].y - mu * acc[e].y);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      o[(t + NT * e) * n + col] = q[e];
+      sig += (double)pv[e].x * (double)q[e].x + (double)pv[e].y * (double)q[e].y;
     }
   }
-  if (mode == CA_PCG) {
+  if (MODE == CA_PCG) {
     sig = block_sum_f64(sig, red);
     if (threadIdx.x == 0) {
       part_ptr(w.part, s, P_SIGMA)[blockIdx.x] = sig;
@@ -212,7 +266,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
 // PCG vector update + residual norm, then the first pass of M^{-1} r (row
 // FFTs), one row tile per workgroup.
 //   RU_SETUP : r = b - q (q = A x0); ||b||^2 and ||r||^2 partials
-//   RU_UPDATE: alpha = rho / sigma; x += alpha pn; r -= alpha q; p = pn
+//   RU_UPDATE: alpha = rho / sigma; x += alpha pn; r -= alpha q
 // Circulant / learned: t = row-FFT(r).  None / Jacobi: rho' = Re(r^H z)
 // partial with z = r or z = r / diag(A).
 // ----------------------------------------------------------------------------
@@ -224,6 +278,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
                                                                    float2* __restrict__ tout) {
   constexpr int NT = RowCfg<N>::NT, E = RowCfg<N>::E;
   __shared__ float2 lds[RowCfg<N>::LDS];
+  __shared__ float2 s_tw[N];
   __shared__ double red[16];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -231,6 +286,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
   const int t = threadIdx.x % NT, rr_ = threadIdx.x / NT;
   const int i = blockIdx.x * kRowRR + rr_;
   const long long rowbase = sd.img + (long long)i * N;
+  if (pk != PK_NONE && pk != PK_JACOBI) stage_twiddles<N, RowCfg<N>::THREADS>(s_tw, w.tw);
 
   int it = 0;
   float alpha = 0.f;
@@ -264,7 +320,6 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
       x[idx] = make_float2(xv.x + alpha * pnv.x, xv.y + alpha * pnv.y);
       const float2 ro = r[idx], qv = q[idx];
       rv = make_float2(ro.x - alpha * qv.x, ro.y - alpha * qv.y);
-      p[idx] = pnv;
     } else {
       const float2 bv = b[idx], qv = q[idx];
       rv = csub(bv, qv);
@@ -288,8 +343,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
     rhop = block_sum_f64(rhop, red);
     if (threadIdx.x == 0) part_ptr(w.part, s, rho_slot)[blockIdx.x] = rhop;
   } else {
-    const float2* __restrict__ tw = w.tw + tw_offset(N);
-    fft<N, -1, RowLay<N>>(v, t, lds, rr_, tw);
+    fft<N, -1, RowLay<N>>(v, t, lds, rr_, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) tout[rowbase + t + NT * e] = v[e];
   }
@@ -306,6 +360,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_precond(Ws w, int us
                                                                      float2* __restrict__ tbuf) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
   __shared__ float2 lds[M * T];
+  __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
   if (use_state) {
@@ -320,14 +375,17 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_precond(Ws w, int us
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int col = blockIdx.x * T + j;
   const long long base = sd.img;
-  const float2* __restrict__ tw = w.tw + tw_offset(M);
+  stage_twiddles<M, ColCfg<M>::THREADS>(s_tw, w.tw);
   float2 v[E];
+  float kv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = tbuf[base + (long long)(t + NT * e) * n + col];
-  fft<M, -1, ColLay<T>>(v, t, lds, j, tw);
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = cscale(v[e], w.kinv[base + (long long)(t + NT * e) * n + col]);
-  fft<M, +1, ColLay<T>>(v, t, lds, j, tw);
+  for (int e = 0; e < E; ++e) kv[e] = w.kinv[base + (long long)(t + NT * e) * n + col];
+  fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = cscale(v[e], kv[e]);
+  fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
   for (int e = 0; e < E; ++e) tbuf[base + (long long)(t + NT * e) * n + col] = v[e];
 }
@@ -340,6 +398,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_z(Ws w, const float2
                                                               const float2* __restrict__ r, float2* __restrict__ z) {
   constexpr int NT = RowCfg<N>::NT, E = RowCfg<N>::E;
   __shared__ float2 lds[RowCfg<N>::LDS];
+  __shared__ float2 s_tw[N];
   __shared__ double red[16];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -348,11 +407,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_z(Ws w, const float2
   const int t = threadIdx.x % NT, rr_ = threadIdx.x / NT;
   const int i = blockIdx.x * kRowRR + rr_;
   const long long rowbase = sd.img + (long long)i * N;
-  const float2* __restrict__ tw = w.tw + tw_offset(N);
+  stage_twiddles<N, RowCfg<N>::THREADS>(s_tw, w.tw);
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = tbuf[rowbase + t + NT * e];
-  fft<N, +1, RowLay<N>>(v, t, lds, rr_, tw);
+  fft<N, +1, RowLay<N>>(v, t, lds, rr_, s_tw);
   double rho = 0.0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -374,11 +433,12 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
                                                                 float2* __restrict__ out) {
   constexpr int NT = RowCfg<N>::NT, E = RowCfg<N>::E;
   __shared__ float2 lds[RowCfg<N>::LDS];
+  __shared__ float2 s_tw[N];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
   const int t = threadIdx.x % NT, rr_ = threadIdx.x / NT;
   const int i = blockIdx.x * kRowRR + rr_;
-  const float2* __restrict__ tw = w.tw + tw_offset(N);
+  stage_twiddles<N, RowCfg<N>::THREADS>(s_tw, w.tw);
   const int ncoil = ncoil_mode ? sd.nc : 1;
   const long long plane = (long long)sd.m * N;
   const uint8_t* mk = w.mask + sd.mask;
@@ -394,7 +454,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
       }
       v[e] = a;
     }
-    fft<N, DIR, RowLay<N>>(v, t, lds, rr_, tw);
+    fft<N, DIR, RowLay<N>>(v, t, lds, rr_, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) out[rowbase + t + NT * e] = v[e];
   }
@@ -406,16 +466,17 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_fft(Ws w, const floa
                                                                 float2* __restrict__ out) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
   __shared__ float2 lds[M * T];
+  __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
   const int n = sd.n;
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int col = blockIdx.x * T + j;
-  const float2* __restrict__ tw = w.tw + tw_offset(M);
+  stage_twiddles<M, ColCfg<M>::THREADS>(s_tw, w.tw);
   float2 v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = in[sd.img + (long long)(t + NT * e) * n + col];
-  fft<M, DIR, ColLay<T>>(v, t, lds, j, tw);
+  fft<M, DIR, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
   for (int e = 0; e < E; ++e) out[sd.img + (long long)(t + NT * e) * n + col] = v[e];
 }
@@ -432,12 +493,13 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
                                                                      float2* __restrict__ x) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
   __shared__ float2 lds[M * T];
+  __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
   const int n = sd.n;
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int col = blockIdx.x * T + j;
-  const float2* __restrict__ tw = w.tw + tw_offset(M);
+  stage_twiddles<M, ColCfg<M>::THREADS>(s_tw, w.tw);
   const float scale = 1.0f / sqrtf((float)M * (float)n);
   float2 acc[E];
   float sos[E];
@@ -451,7 +513,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = coil_rows[cb + (long long)(t + NT * e) * n + col];
-    fft<M, +1, ColLay<T>>(v, t, lds, j, tw);
+    fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const float2 mc = cscale(v[e], scale);
@@ -483,12 +545,13 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, dou
                                                                         float* __restrict__ energy) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
   __shared__ float2 lds[M * T];
+  __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
   const int n = sd.n;
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int col = blockIdx.x * T + j;
-  const float2* __restrict__ tw = w.tw + tw_offset(M);
+  stage_twiddles<M, ColCfg<M>::THREADS>(s_tw, w.tw);
   double pw[E];
   float en[E];
 #pragma unroll
@@ -504,7 +567,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, dou
       v[e] = w.sens[cb + (long long)(t + NT * e) * n + col];
       en[e] += cabs2(v[e]);
     }
-    fft<M, -1, ColLay<T>>(v, t, lds, j, tw);
+    fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) pw[e] += (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
   }
@@ -528,10 +591,17 @@ hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, i
                             float2* g, const float2* g1) {
   const dim3 grid(L.n / kColT, L.count);
   switch (L.m) {
-#define PICS_CASE(M)                                                                                          \
-  case M:                                                                                                     \
-    hipLaunchKernelGGL(k_col_apply<M>, grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, mode, terms, pk, tol, \
-                       xin, zsrc, pold, pn, out, g, g1);                                                      \
+#define PICS_CASE(M)                                                                                         \
+  case M:                                                                                                    \
+    if (mode == CA_PCG)                                                                                      \
+      hipLaunchKernelGGL((k_col_apply<M, CA_PCG>), grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, terms, pk, \
+                         tol, xin, zsrc, pold, pn, out, g, g1);                                              \
+    else if (mode == CA_OUTER)                                                                               \
+      hipLaunchKernelGGL((k_col_apply<M, CA_OUTER>), grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, terms,   \
+                         pk, tol, xin, zsrc, pold, pn, out, g, g1);                                          \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_col_apply<M, CA_APPLY>), grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, terms,   \
+                         pk, tol, xin, zsrc, pold, pn, out, g, g1);                                          \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE

@@ -4,6 +4,8 @@
 //
 // Launch shape: grid (blocks, nslices), a grid-stride loop over one slice's
 // pixels per grid.y, so slices of different sizes share one launch.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace pics {
@@ -81,12 +83,13 @@ __global__ __launch_bounds__(256) void k_pcg_check(Ws w, double tol, int setup, 
 // v = D x + b;  d = shrink(v, 1/lam);  b <- v - d;  u = d - b (the next
 // right-hand side uses D^H u).  With no wavelet the same is done on x itself
 // with threshold 1/gam.
-__global__ __launch_bounds__(256) void k_tv_shrink(Ws w, const float2* __restrict__ x, float2* __restrict__ bx,
-                                                   float2* __restrict__ by, float2* __restrict__ ux,
-                                                   float2* __restrict__ uy, float2* __restrict__ bw,
-                                                   float2* __restrict__ uw) {
+__global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, const float2* __restrict__ x,
+                                                   float2* __restrict__ bx, float2* __restrict__ by,
+                                                   float2* __restrict__ ux, float2* __restrict__ uy,
+                                                   float2* __restrict__ bw, float2* __restrict__ uw) {
   const int s = blockIdx.y;
   const SliceDev sd = w.sl[s];
+  if (only_nowavelet && sd.levels > 0 && sd.wavelet != 0) return;
   const int m = sd.m, n = sd.n;
   const long long np = (long long)m * n;
   const float tl = 1.0f / sd.lam, tg = 1.0f / sd.gam;
@@ -175,75 +178,148 @@ __device__ __forceinline__ void coef_out(const SliceDev& sd, const WaveArgs& a, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_wavelet(Ws w, WaveArgs a) {
+// Both passes of one level in a workgroup: an output tile of kWT x kWT
+// coefficients in each of the four bands, from an input tile of
+// (2 kWT + 7)^2 pixels (filter support plus, at level 0, the row above and the
+// column to the left for the fused TV step), all with periodic wrap.
+constexpr int kWT = 16;
+constexpr int kWIn = 2 * kWT + 7;  // 39: 1 TV halo + 2 kWT + 6 filter halo
+
+__global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
+  __shared__ float2 tile[kWIn][kWIn + 1];
+  __shared__ float2 rowb[kWIn][2 * kWT + 1];
   const int s = blockIdx.y;
   const SliceDev sd = w.sl[s];
   if (sd.wavelet == 0 || a.level >= sd.levels) return;
   const int n = sd.n;
   const int ml = sd.m >> a.level, nl = n >> a.level;
   const int mh = ml / 2, nh = nl / 2;
-  const int K = filt_len(sd.wavelet);
+  const int tcols = (nh + kWT - 1) / kWT, trows = (mh + kWT - 1) / kWT;
+  if ((int)blockIdx.x >= tcols * trows) return;
+  const int k0 = (blockIdx.x / tcols) * kWT, c0 = (blockIdx.x % tcols) * kWT;
   const long long o = sd.img;
   const bool lastlev = (a.level == sd.levels - 1);
-  long long items;
-  if (!a.inverse) items = a.pass == 0 ? (long long)ml * nh : (long long)mh * nl;
-  else items = (long long)ml * nl;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < items;
-       p += (long long)gridDim.x * blockDim.x) {
-    if (!a.inverse && a.pass == 0) {
-      const int i = int(p / nh), k = int(p % nh);
-      float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
-      for (int t = 0; t < K; ++t) {
-        const float2 v = a.in[o + (long long)i * n + (2 * k + t) % nl];
-        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
-        lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
-        hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
+  const int K = filt_len(sd.wavelet);
+  for (int idx = threadIdx.x; idx < kWIn * kWIn; idx += blockDim.x) {
+    const int ra = idx / kWIn, cb = idx % kWIn;
+    const int r = (2 * k0 - 1 + ra + ml) % ml, c = (2 * c0 - 1 + cb + nl) % nl;
+    tile[ra][cb] = a.in[o + (long long)r * n + c];
+  }
+  __syncthreads();
+  // along axis 1
+  for (int idx = threadIdx.x; idx < (kWIn - 1) * kWT; idx += blockDim.x) {
+    const int ra = 1 + idx / kWT, c = idx % kWT;
+    float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+    for (int t = 0; t < K; ++t) {
+      const float2 v = tile[ra][1 + 2 * c + t];
+      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+      lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
+      hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
+    }
+    rowb[ra][c] = lo;
+    rowb[ra][kWT + c] = hi;
+  }
+  __syncthreads();
+  // along axis 0, then the band placement (Mallat layout)
+  for (int idx = threadIdx.x; idx < kWT * 2 * kWT; idx += blockDim.x) {
+    const int k = idx / (2 * kWT), cp = idx % (2 * kWT);
+    const int half = cp / kWT, gk = k0 + k, gc = c0 + (cp % kWT);
+    if (gk >= mh || gc >= nh) continue;
+    float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+    for (int t = 0; t < K; ++t) {
+      const float2 v = rowb[1 + 2 * k + t][cp];
+      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+      lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
+      hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
+    }
+    const long long plo = o + (long long)gk * n + half * nh + gc;
+    const long long phi = o + (long long)(mh + gk) * n + half * nh + gc;
+    if (half == 0 && !lastlev) a.out[plo] = lo;  // approximation block feeds the next level
+    else coef_out(sd, a, plo, lo);
+    coef_out(sd, a, phi, hi);
+  }
+  // level 0: Algorithm 1 steps 6, 7, 9, 10 on the 2 kWT x 2 kWT pixel block
+  if (tv.enabled && a.level == 0) {
+    const float thr = 1.0f / sd.lam;
+    for (int idx = threadIdx.x; idx < 4 * kWT * kWT; idx += blockDim.x) {
+      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
+      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+      if (i >= ml || jj >= nl) continue;
+      const long long pp = o + (long long)i * n + jj;
+      const float2 xc = tile[1 + ia][1 + jb], xu = tile[ia][1 + jb], xl = tile[1 + ia][jb];
+      {
+        const float2 v = cadd(csub(xc, xu), tv.bx[pp]);
+        const float2 d = shrink(v, thr);
+        const float2 b = csub(v, d);
+        tv.bx[pp] = b;
+        tv.ux[pp] = csub(d, b);
       }
-      a.out[o + (long long)i * n + k] = lo;
-      a.out[o + (long long)i * n + nh + k] = hi;
-    } else if (!a.inverse) {
-      const int k = int(p / nl), j = int(p % nl);
-      float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
-      for (int t = 0; t < K; ++t) {
-        const float2 v = a.in[o + (long long)((2 * k + t) % ml) * n + j];
-        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
-        lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
-        hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
-      }
-      const long long plo = o + (long long)k * n + j, phi = o + (long long)(mh + k) * n + j;
-      if (j < nh && !lastlev) a.out[plo] = lo;  // approximation block for the next level
-      else coef_out(sd, a, plo, lo);
-      coef_out(sd, a, phi, hi);
-    } else if (a.pass == 0) {
-      // synthesis along axis 0: out[i][j] from rows [0, mh) (low) and [mh, ml) (high)
-      const int i = int(p / nl), j = int(p % nl);
-      const float2* lowsrc = (j < nh && !lastlev) ? a.in : a.coef;
-      float2 acc = make_float2(0.f, 0.f);
-      for (int t = (i & 1); t < K; t += 2) {
-        const int k = (((i - t) % ml + ml) % ml) / 2;
-        const float2 lv = lowsrc[o + (long long)k * n + j];
-        const float2 hv = a.coef[o + (long long)(mh + k) * n + j];
-        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
-        acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
-      }
-      a.out[o + (long long)i * n + j] = acc;
-    } else {
-      // synthesis along axis 1 from tmp columns [0, nh) and [nh, nl)
-      const int i = int(p / nl), jj = int(p % nl);
-      float2 acc = make_float2(0.f, 0.f);
-      for (int t = (jj & 1); t < K; t += 2) {
-        const int k = (((jj - t) % nl + nl) % nl) / 2;
-        const float2 lv = a.in[o + (long long)i * n + k];
-        const float2 hv = a.in[o + (long long)i * n + nh + k];
-        const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
-        acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
-      }
-      if (a.level == 0 && a.mode == 1) {
-        a.rhs[o + (long long)i * n + jj] = rhs_at(sd, o, i, jj, a.g, a.ux, a.uy, acc);
-      } else {
-        a.out[o + (long long)i * n + jj] = acc;
+      {
+        const float2 v = cadd(csub(xc, xl), tv.by[pp]);
+        const float2 d = shrink(v, thr);
+        const float2 b = csub(v, d);
+        tv.by[pp] = b;
+        tv.uy[pp] = csub(d, b);
       }
     }
+  }
+}
+
+// Synthesis of one level: a 2 kWT x 2 kWT output pixel block from the four
+// bands' (kWT + 3)^2 coefficient windows; at level 0 in mode 1 the pixel is
+// combined straight into the Split Bregman right-hand side.
+__global__ __launch_bounds__(256) void k_dwt_syn(Ws w, WaveArgs a) {
+  constexpr int WB = kWT + 3;
+  __shared__ float2 bands[4][WB][WB + 1];
+  __shared__ float2 u[2 * kWT][2 * WB + 1];
+  const int s = blockIdx.y;
+  const SliceDev sd = w.sl[s];
+  if (sd.wavelet == 0 || a.level >= sd.levels) return;
+  const int n = sd.n;
+  const int ml = sd.m >> a.level, nl = n >> a.level;
+  const int mh = ml / 2, nh = nl / 2;
+  const int tcols = (nh + kWT - 1) / kWT, trows = (mh + kWT - 1) / kWT;
+  if ((int)blockIdx.x >= tcols * trows) return;
+  const int k0 = (blockIdx.x / tcols) * kWT, c0 = (blockIdx.x % tcols) * kWT;
+  const long long o = sd.img;
+  const bool lastlev = (a.level == sd.levels - 1);
+  const int K = filt_len(sd.wavelet);
+  for (int idx = threadIdx.x; idx < 4 * WB * WB; idx += blockDim.x) {
+    const int b = idx / (WB * WB), rr = (idx / WB) % WB, cc = idx % WB;
+    const int a0 = b >> 1, a1 = b & 1;
+    const int kr = ((k0 - 3 + rr) % mh + mh) % mh, kc = ((c0 - 3 + cc) % nh + nh) % nh;
+    const float2* src = (a0 == 0 && a1 == 0 && !lastlev) ? a.in : a.coef;
+    bands[b][rr][cc] = src[o + (long long)(a0 * mh + kr) * n + a1 * nh + kc];
+  }
+  __syncthreads();
+  // along axis 0
+  for (int idx = threadIdx.x; idx < 2 * kWT * 2 * WB; idx += blockDim.x) {
+    const int ia = idx / (2 * WB), q = idx % (2 * WB);
+    const int a1 = q / WB, cc = q % WB;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int t = (ia & 1); t < K; t += 2) {
+      const int rr = (ia - t) / 2 + 3;
+      const float2 lv = bands[a1][rr][cc], hv = bands[2 + a1][rr][cc];
+      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+      acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
+    }
+    u[ia][q] = acc;
+  }
+  __syncthreads();
+  // along axis 1
+  for (int idx = threadIdx.x; idx < 4 * kWT * kWT; idx += blockDim.x) {
+    const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
+    const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+    if (i >= ml || jj >= nl) continue;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int t = (jb & 1); t < K; t += 2) {
+      const int cc = (jb - t) / 2 + 3;
+      const float2 lv = u[ia][cc], hv = u[ia][WB + cc];
+      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+      acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
+    }
+    if (a.level == 0 && a.mode == 1) a.rhs[o + (long long)i * n + jj] = rhs_at(sd, o, i, jj, a.g, a.ux, a.uy, acc);
+    else a.out[o + (long long)i * n + jj] = acc;
   }
 }
 
@@ -323,9 +399,10 @@ hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol
   return hipGetLastError();
 }
 
-hipError_t launch_tv_shrink(const Simple& S, const Ws& w, const float2* x, float2* bx, float2* by, float2* ux,
-                            float2* uy, float2* bw, float2* uw) {
-  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, x, bx, by, ux, uy, bw, uw);
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const float2* x, float2* bx,
+                            float2* by, float2* ux, float2* uy, float2* bw, float2* uw) {
+  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, only_nowavelet, x, bx, by, ux, uy, bw,
+                     uw);
   return hipGetLastError();
 }
 
@@ -335,8 +412,17 @@ hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, c
   return hipGetLastError();
 }
 
-hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a) {
-  hipLaunchKernelGGL(k_wavelet, simple_grid(S), dim3(256), 0, S.stream, w, a);
+int wavelet_tiles(int m, int n, int level) {
+  const int mh = (m >> level) / 2, nh = (n >> level) / 2;
+  return ((mh + kWT - 1) / kWT) * ((nh + kWT - 1) / kWT);
+}
+
+hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a, const TvArgs& tv, int tiles) {
+  const dim3 grid((unsigned)std::max(1, tiles), S.nslices);
+  if (a.inverse)
+    hipLaunchKernelGGL(k_dwt_syn, grid, dim3(256), 0, S.stream, w, a);
+  else
+    hipLaunchKernelGGL(k_dwt_ana, grid, dim3(256), 0, S.stream, w, a, tv);
   return hipGetLastError();
 }
 
