@@ -185,24 +185,40 @@ __device__ __forceinline__ void coef_out(const SliceDev& sd, const WaveArgs& a, 
 constexpr int kWT = 16;
 constexpr int kWIn = 2 * kWT + 7;  // 39: 1 TV halo + 2 kWT + 6 filter halo
 
-__global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
-  __shared__ float2 tile[kWIn][kWIn + 1];
-  __shared__ float2 rowb[kWIn][2 * kWT + 1];
-  const int s = blockIdx.y;
-  const SliceDev sd = w.sl[s];
-  if (sd.wavelet == 0 || a.level >= sd.levels) return;
+template <int K>
+struct Filt {
+  float h[K], g[K];
+  __device__ __forceinline__ Filt() {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      h[t] = K == 2 ? c_haar[t] : c_db4[t];
+      const float v = K == 2 ? c_haar[K - 1 - t] : c_db4[K - 1 - t];
+      g[t] = (t & 1) ? -v : v;
+    }
+  }
+};
+
+// index i in [-L, 2L) folded into [0, L); any i when `small`
+__device__ __forceinline__ int wrap(int i, int L, bool small) {
+  if (small) return ((i % L) + L) % L;
+  return i < 0 ? i + L : (i >= L ? i - L : i);
+}
+
+template <int K>
+__device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs& a, const TvArgs& tv,
+                                             float2 (*tile)[kWIn + 1], float2 (*rowb)[2 * kWT + 1]) {
   const int n = sd.n;
   const int ml = sd.m >> a.level, nl = n >> a.level;
   const int mh = ml / 2, nh = nl / 2;
-  const int tcols = (nh + kWT - 1) / kWT, trows = (mh + kWT - 1) / kWT;
-  if ((int)blockIdx.x >= tcols * trows) return;
+  const int tcols = (nh + kWT - 1) / kWT;
   const int k0 = (blockIdx.x / tcols) * kWT, c0 = (blockIdx.x % tcols) * kWT;
   const long long o = sd.img;
   const bool lastlev = (a.level == sd.levels - 1);
-  const int K = filt_len(sd.wavelet);
+  const bool small = ml < kWIn || nl < kWIn;
+  const Filt<K> f;
   for (int idx = threadIdx.x; idx < kWIn * kWIn; idx += blockDim.x) {
     const int ra = idx / kWIn, cb = idx % kWIn;
-    const int r = (2 * k0 - 1 + ra + ml) % ml, c = (2 * c0 - 1 + cb + nl) % nl;
+    const int r = wrap(2 * k0 - 1 + ra, ml, small), c = wrap(2 * c0 - 1 + cb, nl, small);
     tile[ra][cb] = a.in[o + (long long)r * n + c];
   }
   __syncthreads();
@@ -210,11 +226,11 @@ __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
   for (int idx = threadIdx.x; idx < (kWIn - 1) * kWT; idx += blockDim.x) {
     const int ra = 1 + idx / kWT, c = idx % kWT;
     float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+#pragma unroll
     for (int t = 0; t < K; ++t) {
       const float2 v = tile[ra][1 + 2 * c + t];
-      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
-      lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
-      hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
+      lo = make_float2(lo.x + f.h[t] * v.x, lo.y + f.h[t] * v.y);
+      hi = make_float2(hi.x + f.g[t] * v.x, hi.y + f.g[t] * v.y);
     }
     rowb[ra][c] = lo;
     rowb[ra][kWT + c] = hi;
@@ -226,11 +242,11 @@ __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
     const int half = cp / kWT, gk = k0 + k, gc = c0 + (cp % kWT);
     if (gk >= mh || gc >= nh) continue;
     float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+#pragma unroll
     for (int t = 0; t < K; ++t) {
       const float2 v = rowb[1 + 2 * k + t][cp];
-      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
-      lo = make_float2(lo.x + h * v.x, lo.y + h * v.y);
-      hi = make_float2(hi.x + g * v.x, hi.y + g * v.y);
+      lo = make_float2(lo.x + f.h[t] * v.x, lo.y + f.h[t] * v.y);
+      hi = make_float2(hi.x + f.g[t] * v.x, hi.y + f.g[t] * v.y);
     }
     const long long plo = o + (long long)gk * n + half * nh + gc;
     const long long phi = o + (long long)(mh + gk) * n + half * nh + gc;
@@ -247,15 +263,16 @@ __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
       if (i >= ml || jj >= nl) continue;
       const long long pp = o + (long long)i * n + jj;
       const float2 xc = tile[1 + ia][1 + jb], xu = tile[ia][1 + jb], xl = tile[1 + ia][jb];
+      const float2 bxv = tv.bx[pp], byv = tv.by[pp];
       {
-        const float2 v = cadd(csub(xc, xu), tv.bx[pp]);
+        const float2 v = cadd(csub(xc, xu), bxv);
         const float2 d = shrink(v, thr);
         const float2 b = csub(v, d);
         tv.bx[pp] = b;
         tv.ux[pp] = csub(d, b);
       }
       {
-        const float2 v = cadd(csub(xc, xl), tv.by[pp]);
+        const float2 v = cadd(csub(xc, xl), byv);
         const float2 d = shrink(v, thr);
         const float2 b = csub(v, d);
         tv.by[pp] = b;
@@ -265,42 +282,54 @@ __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
+  __shared__ float2 tile[kWIn][kWIn + 1];
+  __shared__ float2 rowb[kWIn][2 * kWT + 1];
+  const SliceDev sd = w.sl[blockIdx.y];
+  if (sd.wavelet == 0 || a.level >= sd.levels) return;
+  const int mh = (sd.m >> a.level) / 2, nh = (sd.n >> a.level) / 2;
+  if ((int)blockIdx.x >= ((nh + kWT - 1) / kWT) * ((mh + kWT - 1) / kWT)) return;
+  if (sd.wavelet == 1) dwt_ana_tile<2>(sd, a, tv, tile, rowb);
+  else dwt_ana_tile<8>(sd, a, tv, tile, rowb);
+}
+
 // Synthesis of one level: a 2 kWT x 2 kWT output pixel block from the four
 // bands' (kWT + 3)^2 coefficient windows; at level 0 in mode 1 the pixel is
 // combined straight into the Split Bregman right-hand side.
-__global__ __launch_bounds__(256) void k_dwt_syn(Ws w, WaveArgs a) {
-  constexpr int WB = kWT + 3;
-  __shared__ float2 bands[4][WB][WB + 1];
-  __shared__ float2 u[2 * kWT][2 * WB + 1];
-  const int s = blockIdx.y;
-  const SliceDev sd = w.sl[s];
-  if (sd.wavelet == 0 || a.level >= sd.levels) return;
+constexpr int kWB = kWT + 3;
+
+template <int K>
+__device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs& a, float2 (*bands)[kWB][kWB + 1],
+                                             float2 (*u)[2 * kWB + 1]) {
   const int n = sd.n;
   const int ml = sd.m >> a.level, nl = n >> a.level;
   const int mh = ml / 2, nh = nl / 2;
-  const int tcols = (nh + kWT - 1) / kWT, trows = (mh + kWT - 1) / kWT;
-  if ((int)blockIdx.x >= tcols * trows) return;
+  const int tcols = (nh + kWT - 1) / kWT;
   const int k0 = (blockIdx.x / tcols) * kWT, c0 = (blockIdx.x % tcols) * kWT;
   const long long o = sd.img;
   const bool lastlev = (a.level == sd.levels - 1);
-  const int K = filt_len(sd.wavelet);
-  for (int idx = threadIdx.x; idx < 4 * WB * WB; idx += blockDim.x) {
-    const int b = idx / (WB * WB), rr = (idx / WB) % WB, cc = idx % WB;
+  const bool small = mh < kWB || nh < kWB;
+  const Filt<K> f;
+  for (int idx = threadIdx.x; idx < 4 * kWB * kWB; idx += blockDim.x) {
+    const int b = idx / (kWB * kWB), rr = (idx / kWB) % kWB, cc = idx % kWB;
     const int a0 = b >> 1, a1 = b & 1;
-    const int kr = ((k0 - 3 + rr) % mh + mh) % mh, kc = ((c0 - 3 + cc) % nh + nh) % nh;
+    const int kr = wrap(k0 - 3 + rr, mh, small), kc = wrap(c0 - 3 + cc, nh, small);
     const float2* src = (a0 == 0 && a1 == 0 && !lastlev) ? a.in : a.coef;
     bands[b][rr][cc] = src[o + (long long)(a0 * mh + kr) * n + a1 * nh + kc];
   }
   __syncthreads();
   // along axis 0
-  for (int idx = threadIdx.x; idx < 2 * kWT * 2 * WB; idx += blockDim.x) {
-    const int ia = idx / (2 * WB), q = idx % (2 * WB);
-    const int a1 = q / WB, cc = q % WB;
+  for (int idx = threadIdx.x; idx < 2 * kWT * 2 * kWB; idx += blockDim.x) {
+    const int ia = idx / (2 * kWB), q = idx % (2 * kWB);
+    const int a1 = q / kWB, cc = q % kWB;
     float2 acc = make_float2(0.f, 0.f);
-    for (int t = (ia & 1); t < K; t += 2) {
+#pragma unroll
+    for (int tt = 0; tt < K / 2; ++tt) {
+      const int t = 2 * tt + (ia & 1);
       const int rr = (ia - t) / 2 + 3;
       const float2 lv = bands[a1][rr][cc], hv = bands[2 + a1][rr][cc];
-      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+      const float h = (ia & 1) ? f.h[2 * tt + 1] : f.h[2 * tt];
+      const float g = (ia & 1) ? f.g[2 * tt + 1] : f.g[2 * tt];
       acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
     }
     u[ia][q] = acc;
@@ -312,15 +341,29 @@ __global__ __launch_bounds__(256) void k_dwt_syn(Ws w, WaveArgs a) {
     const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
     if (i >= ml || jj >= nl) continue;
     float2 acc = make_float2(0.f, 0.f);
-    for (int t = (jb & 1); t < K; t += 2) {
+#pragma unroll
+    for (int tt = 0; tt < K / 2; ++tt) {
+      const int t = 2 * tt + (jb & 1);
       const int cc = (jb - t) / 2 + 3;
-      const float2 lv = u[ia][cc], hv = u[ia][WB + cc];
-      const float h = filt_h(sd.wavelet, t), g = filt_g(sd.wavelet, t);
+      const float2 lv = u[ia][cc], hv = u[ia][kWB + cc];
+      const float h = (jb & 1) ? f.h[2 * tt + 1] : f.h[2 * tt];
+      const float g = (jb & 1) ? f.g[2 * tt + 1] : f.g[2 * tt];
       acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
     }
     if (a.level == 0 && a.mode == 1) a.rhs[o + (long long)i * n + jj] = rhs_at(sd, o, i, jj, a.g, a.ux, a.uy, acc);
     else a.out[o + (long long)i * n + jj] = acc;
   }
+}
+
+__global__ __launch_bounds__(256) void k_dwt_syn(Ws w, WaveArgs a) {
+  __shared__ float2 bands[4][kWB][kWB + 1];
+  __shared__ float2 u[2 * kWT][2 * kWB + 1];
+  const SliceDev sd = w.sl[blockIdx.y];
+  if (sd.wavelet == 0 || a.level >= sd.levels) return;
+  const int mh = (sd.m >> a.level) / 2, nh = (sd.n >> a.level) / 2;
+  if ((int)blockIdx.x >= ((nh + kWT - 1) / kWT) * ((mh + kWT - 1) / kWT)) return;
+  if (sd.wavelet == 1) dwt_syn_tile<2>(sd, a, bands, u);
+  else dwt_syn_tile<8>(sd, a, bands, u);
 }
 
 // ------------------------------------------------------ spectrum assembly
