@@ -154,9 +154,17 @@ int pcg_solve(pics_ctx* ctx, const void* b, void* x, double tol, int32_t maxit, 
 int split_bregman_recon(pics_ctx* ctx, const void* kspace, int32_t n_outer, int32_t n_inner, double tol,
                         int32_t maxit, const int32_t* lock_iters, void* x_out, int32_t* pcg_iters);
 
-/* Options: PICS_OPT_POLL_CHUNK = PCG iterations enqueued between host
- * convergence polls (first poll; later polls double it, up to 32). */
+/* Options.
+ * PICS_OPT_POLL_CHUNK: PCG iterations enqueued between host convergence polls
+ *   (first poll; later polls double it, up to 32).  Default 2.
+ * PICS_OPT_GRAPH_BUDGET: split_bregman_recon runs the first outer iteration
+ *   host-polled and replays the others from one captured HIP graph whose PCG
+ *   solves carry this many iterations (kernels of converged slices exit at
+ *   entry).  If a solve needs more, the reconstruction is redone host-polled,
+ *   so results never depend on the budget; the budget is then raised.
+ *   0 disables the graph.  Default 2. */
 #define PICS_OPT_POLL_CHUNK 1
+#define PICS_OPT_GRAPH_BUDGET 2
 int pics_set_option(pics_ctx* ctx, int32_t key, int64_t value);
 
 const char* pics_status_string(int status);

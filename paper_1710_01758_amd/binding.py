@@ -24,6 +24,7 @@ WAVELET = {"none": 0, "haar": 1, "db4": 2}
 PRECOND = {"none": 0, "jacobi": 1, "circulant": 2, "learned": 3}
 TERM_DATA, TERM_TV, TERM_GAMMA, TERM_ALL = 1, 2, 4, 7
 OPT_POLL_CHUNK = 1
+OPT_GRAPH_BUDGET = 2
 
 
 class PicsError(RuntimeError):

@@ -56,6 +56,25 @@ struct pics_ctx {
   int pk = PK_NONE;
   int poll_chunk = 2;
   std::string err;
+
+  // Split Bregman outer iterations replayed from a captured graph
+  int graph_budget = 2;          // PCG iterations per solve inside the graph (0: host-polled only)
+  int* solve_counter = nullptr;  // device: history row of the next solve
+  int* hist = nullptr;           // device: [solves][nslices] iterations, then [solves][nslices] status
+  long long hist_cap = 0;
+  std::vector<int> hist_host;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  struct GraphKey {
+    const void* x;
+    double tol;
+    int budget, pk, n_inner;
+    const int* hist;
+    bool operator==(const GraphKey& o) const {
+      return x == o.x && tol == o.tol && budget == o.budget && pk == o.pk && n_inner == o.n_inner && hist == o.hist;
+    }
+  } graph_key{};
+  int graph_fallbacks = 0;       // solves that exceeded the budget (reconstruction redone host-polled)
 };
 
 namespace {
@@ -207,6 +226,11 @@ int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
     c->poll_chunk = (int)value;
     return PICS_OK;
   }
+  if (key == PICS_OPT_GRAPH_BUDGET) {
+    if (value < 0 || value > 64) return fail(c, PICS_ERR_INVALID, "graph budget out of range");
+    c->graph_budget = (int)value;
+    return PICS_OK;
+  }
   return fail(c, PICS_ERR_INVALID, "unknown option %d", key);
 }
 
@@ -302,6 +326,7 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   add((void**)&c->pbar, sizeof(double) * std::max(1LL, c->aux_total));
   add((void**)&c->st, sizeof(PcgState) * nslices);
   add((void**)&c->bad, sizeof(int));
+  add((void**)&c->solve_counter, sizeof(int));
   size_t total = 0;
   for (auto& pr : plan) total += pr.second;
   if (hipMalloc(&c->block, total) != hipSuccess) {
@@ -352,6 +377,9 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
 int pics_destroy(pics_ctx* c) {
   if (!c) return PICS_ERR_INVALID;
   hipStreamSynchronize(c->stream);
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  if (c->hist) hipFree(c->hist);
   if (c->lock_block) hipFree(c->lock_block);
   if (c->st_host) hipHostFree(c->st_host);
   if (c->flag_host) hipHostFree(c->flag_host);
@@ -441,19 +469,26 @@ int pics_wavelet(pics_ctx* c, const void* in, void* out, int32_t inverse) {
 // ---------------------------------------------------------------- PCG driver
 namespace {
 
-// Enqueue one PCG solve for every slice and wait for it.  When q_valid, q
-// already holds A x (the Split Bregman outer update computes it) and the
-// set-up product is skipped.
-int pcg_run(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, const int* maxit_dev, int maxit_max,
-            bool q_valid) {
+// Launch helpers read c->stream; capture swaps in the private capture stream.
+struct StreamSwap {
+  pics_ctx* c;
+  hipStream_t saved;
+  StreamSwap(pics_ctx* cc, hipStream_t s) : c(cc), saved(cc->stream) { c->stream = s; }
+  ~StreamSwap() { c->stream = saved; }
+};
+
+// PCG set-up: r = b - A x0 (q already holds A x0 when q_valid), ||b||, the
+// zero-iteration test, and z_0 = M^{-1} r_0 with its rho partials.
+int enq_pcg_setup(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, const int* maxit_dev,
+                  bool q_valid) {
   const Ws w = make_ws(c);
   const int pk = c->pk;
   const bool circ = pk == PK_CIRC || pk == PK_LEARNED;
   HIPCHK(c, launch_pcg_reset(c->stream, w, c->nslices, maxit, maxit_dev));
   if (!q_valid)
     for (auto& g : c->groups)
-      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr,
-                                 nullptr, nullptr, c->q, nullptr, nullptr));
+      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr,
+                                 nullptr, c->q, nullptr, nullptr));
   for (auto& g : c->groups)
     HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
                                 c->t));
@@ -462,39 +497,35 @@ int pcg_run(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, cons
     for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
     for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
   }
+  return PICS_OK;
+}
+
+// PCG iterations k0 .. k0 + count - 1.  Search directions alternate between
+// two buffers: iteration k reads p_k from pbuf[k & 1] and writes p_{k+1} to
+// pbuf[(k + 1) & 1].  Every kernel returns at entry for finished slices.
+int enq_pcg_iters(pics_ctx* c, float2* x, double tol, int k0, int count) {
+  const int pk = c->pk;
+  const bool circ = pk == PK_CIRC || pk == PK_LEARNED;
   const float2* zsrc = circ ? c->z : c->r;
-  // search directions alternate between two buffers: iteration k reads
-  // p_k from pbuf[k & 1] and writes p_{k+1} to pbuf[(k + 1) & 1]
   float2* pbuf[2] = {c->p, c->pn};
-  int done_iters = 0;
-  int chunk = std::max(1, c->poll_chunk);
-  if (maxit_dev) chunk = std::max(1, maxit_max);  // iteration-locked: one poll at the end
-  while (true) {
-    const int todo = std::min(chunk, maxit_max - done_iters);
-    for (int k = 0; k < todo; ++k) {
-      const int kk = done_iters + k;
-      float2* pold = pbuf[kk & 1];
-      float2* pnew = pbuf[(kk + 1) & 1];
-      for (auto& g : c->groups)
-        HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, pold,
-                                   pnew, c->q, nullptr, nullptr));
-      for (auto& g : c->groups)
-        HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, pnew,
-                                    nullptr, c->t));
-      if (circ) {
-        for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
-        for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
-      }
+  for (int k = k0; k < k0 + count; ++k) {
+    float2* pold = pbuf[k & 1];
+    float2* pnew = pbuf[(k + 1) & 1];
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, pold,
+                                 pnew, c->q, nullptr, nullptr));
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, pnew,
+                                  nullptr, c->t));
+    if (circ) {
+      for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
+      for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
     }
-    done_iters += std::max(todo, 0);
-    HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 0, x));
-    HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(PcgState) * c->nslices, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    bool all = true;
-    for (int s = 0; s < c->nslices; ++s) all = all && c->st_host[s].done;
-    if (all || done_iters >= maxit_max) break;
-    chunk = std::min(chunk * 2, 32);
   }
+  return PICS_OK;
+}
+
+int pcg_status_rc(pics_ctx* c, double tol) {
   int rc = PICS_OK;
   for (int s = 0; s < c->nslices; ++s) {
     const PcgState& st = c->st_host[s];
@@ -503,6 +534,33 @@ int pcg_run(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, cons
   }
   if (rc < 0) return fail(c, rc, "PCG failed: %s", pics_status_string(rc));
   return rc;
+}
+
+// One PCG solve for every slice, polled from the host: iterations are
+// enqueued in chunks of 2, 4, 8, ... (at most 32) with the per-slice state
+// copied back after each chunk.
+int pcg_run(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, const int* maxit_dev, int maxit_max,
+            bool q_valid) {
+  const Ws w = make_ws(c);
+  int rc = enq_pcg_setup(c, b, x, tol, maxit, maxit_dev, q_valid);
+  if (rc) return rc;
+  int done_iters = 0;
+  int chunk = std::max(1, c->poll_chunk);
+  if (maxit_dev) chunk = std::max(1, maxit_max);  // iteration-locked: one poll at the end
+  while (true) {
+    const int todo = std::max(0, std::min(chunk, maxit_max - done_iters));
+    rc = enq_pcg_iters(c, x, tol, done_iters, todo);
+    if (rc) return rc;
+    done_iters += todo;
+    HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 0, x));
+    HIPCHK(c, hipMemcpyAsync(c->st_host, c->st, sizeof(PcgState) * c->nslices, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool all = true;
+    for (int s = 0; s < c->nslices; ++s) all = all && c->st_host[s].done;
+    if (all || done_iters >= maxit_max) break;
+    chunk = std::min(chunk * 2, 32);
+  }
+  return pcg_status_rc(c, tol);
 }
 
 int ensure_lock(pics_ctx* c, long long count) {
@@ -516,6 +574,94 @@ int ensure_lock(pics_ctx* c, long long count) {
   HIPCHK(c, hipMalloc(&c->lock_block, sizeof(int) * count));
   c->lock_dev = (int*)c->lock_block;
   c->lock_cap = (int)count;
+  return PICS_OK;
+}
+
+int ensure_hist(pics_ctx* c, long long solves) {
+  const long long need = 2 * solves * c->nslices;
+  if (need <= c->hist_cap) return PICS_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->hist) HIPCHK(c, hipFree(c->hist));
+  c->hist = nullptr;
+  HIPCHK(c, hipMalloc((void**)&c->hist, sizeof(int) * need));
+  c->hist_cap = need;
+  return PICS_OK;
+}
+
+// Split Bregman step 4: b = g_j + lam [D_x^H u_x + D_y^H u_y] + gam W^H u_w
+int enq_rhs(pics_ctx* c) {
+  const Ws w = make_ws(c);
+  const Simple S = make_simple(c);
+  if (c->any_nowavelet) HIPCHK(c, launch_rhs_nowavelet(S, w, c->g, c->ux, c->uy, c->uw, c->rhs));
+  if (c->any_wavelet) return wavelet_synthesis(c, c->uw, 1, nullptr, c->g, c->ux, c->uy, c->rhs);
+  return PICS_OK;
+}
+
+// Split Bregman steps 6-11: TV and wavelet shrinks and Bregman updates
+int enq_shrinks(pics_ctx* c, const float2* x) {
+  const Ws w = make_ws(c);
+  const Simple S = make_simple(c);
+  if (c->any_nowavelet) HIPCHK(c, launch_tv_shrink(S, w, 1, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+  if (c->any_wavelet) {
+    TvArgs tv{1, c->bx, c->by, c->ux, c->uy};
+    return wavelet_analysis(c, x, 1, nullptr, c->bw, c->uw, tv);
+  }
+  return PICS_OK;
+}
+
+// Split Bregman steps 13-15 in the image domain: g_{j+1} = g_j + g_1 - A_data x;
+// the same kernel leaves A x in q for the next solve's set-up.
+int enq_outer(pics_ctx* c, float2* x) {
+  for (auto& g : c->groups)
+    HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_OUTER, TERM_ALL, c->pk, 0.0, x, nullptr, nullptr,
+                               nullptr, c->q, c->g, c->g1));
+  return PICS_OK;
+}
+
+// One outer iteration (all inner iterations) with fixed-budget PCG solves,
+// each followed by a record of its per-slice iteration count and status.
+int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
+  const Ws w = make_ws(c);
+  for (int ji = 0; ji < n_inner; ++ji) {
+    int rc = enq_rhs(c);
+    if (rc) return rc;
+    rc = enq_pcg_setup(c, c->rhs, x, tol, budget, nullptr, ji == 0);
+    if (rc) return rc;
+    rc = enq_pcg_iters(c, x, tol, 0, budget);
+    if (rc) return rc;
+    HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 0, x));
+    HIPCHK(c, launch_pcg_record(c->stream, w, c->nslices, c->hist, c->hist + c->hist_cap / 2, c->solve_counter));
+    rc = enq_shrinks(c, x);
+    if (rc) return rc;
+  }
+  return enq_outer(c, x);
+}
+
+int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
+  const pics_ctx::GraphKey key{x, tol, budget, c->pk, n_inner, c->hist};
+  if (c->graph_exec && c->graph_key == key) return PICS_OK;
+  if (c->graph_exec) {
+    HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
+    c->graph_exec = nullptr;
+  }
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph;
+  HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc;
+  {
+    StreamSwap sw(c, c->cap_stream);
+    rc = enq_outer_iteration_budgeted(c, x, tol, n_inner, budget);
+  }
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  if (rc) {
+    if (e == hipSuccess) hipGraphDestroy(graph);
+    return rc;
+  }
+  HIPCHK(c, e);
+  const hipError_t ei = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  HIPCHK(c, ei);
+  c->graph_key = key;
   return PICS_OK;
 }
 
@@ -568,56 +714,82 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
     HIPCHK(c, hipMemcpyAsync(c->lock_dev, lock_iters, sizeof(int) * nsolve * c->nslices, hipMemcpyHostToDevice,
                              c->stream));
   }
-  const Ws w = make_ws(c);
-  const Simple S = make_simple(c);
   float2* x = (float2*)x_out;
-  // Algorithm 1, step 1: coil images F^H R y_i, root sum of squares, g_1
-  for (auto& g : c->groups)
-    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, (const float2*)kspace, c->coiltmp));
-  for (auto& g : c->groups) HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, x));
-  for (float2* b : {c->bx, c->by, c->bw, c->ux, c->uy, c->uw})
-    HIPCHK(c, launch_fill(c->stream, b, c->img_total, make_float2(0.f, 0.f)));
-  bool q_valid = false;
-  int rc_all = PICS_OK;
-  for (int jo = 0; jo < n_outer; ++jo) {
-    for (int ji = 0; ji < n_inner; ++ji) {
-      const long long solve = (long long)jo * n_inner + ji;
-      // step 4: b = g_j + lam [D_x^H (d_x - b_x) + D_y^H (d_y - b_y)] + gam W^H (d_w - b_w)
-      if (c->any_nowavelet) HIPCHK(c, launch_rhs_nowavelet(S, w, c->g, c->ux, c->uy, c->uw, c->rhs));
-      if (c->any_wavelet) {
-        const int rc = wavelet_synthesis(c, c->uw, 1, nullptr, c->g, c->ux, c->uy, c->rhs);
-        if (rc) return rc;
-      }
-      // step 5: PCG warm-started at x
-      int rc;
-      if (lock_iters) {
-        int mx = 0;
-        for (int s = 0; s < c->nslices; ++s) mx = std::max(mx, (int)lock_iters[solve * c->nslices + s]);
-        rc = pcg_run(c, c->rhs, x, 0.0, 0, c->lock_dev + solve * c->nslices, mx, q_valid);
-      } else {
-        rc = pcg_run(c, c->rhs, x, tol, maxit, nullptr, maxit, q_valid);
-      }
-      if (rc < 0) return rc;
-      if (rc > 0) rc_all = rc;
-      if (pcg_iters)
-        for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
-      // steps 6-11: TV and wavelet shrink / Bregman updates
-      if (c->any_nowavelet) HIPCHK(c, launch_tv_shrink(S, w, 1, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
-      if (c->any_wavelet) {
-        TvArgs tv{1, c->bx, c->by, c->ux, c->uy};
-        const int rc = wavelet_analysis(c, x, 1, nullptr, c->bw, c->uw, tv);
-        if (rc) return rc;
-      }
-      q_valid = false;
-    }
-    // steps 13-15 in the image domain: g_{j+1} = g_j + g_1 - A_data x; also q = A x
-    for (auto& g : c->groups)
-      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_OUTER, TERM_ALL, c->pk, 0.0, x, nullptr,
-                                 nullptr, nullptr, c->q, c->g, c->g1));
-    q_valid = true;
+  const bool use_graph = !lock_iters && c->graph_budget > 0 && n_outer > 1 && tol > 0.0;
+  if (use_graph) {
+    int rc = ensure_hist(c, nsolve);
+    if (rc) return rc;
   }
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return rc_all;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const bool graph_now = use_graph && attempt == 0;
+    // Algorithm 1, step 1: coil images F^H R y_i, root sum of squares, g_1
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, (const float2*)kspace, c->coiltmp));
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, x));
+    for (float2* b : {c->bx, c->by, c->bw, c->ux, c->uy, c->uw})
+      HIPCHK(c, launch_fill(c->stream, b, c->img_total, make_float2(0.f, 0.f)));
+    bool q_valid = false;
+    int rc_all = PICS_OK;
+    const int host_outer = graph_now ? 1 : n_outer;
+    for (int jo = 0; jo < host_outer; ++jo) {
+      for (int ji = 0; ji < n_inner; ++ji) {
+        const long long solve = (long long)jo * n_inner + ji;
+        int rc = enq_rhs(c);
+        if (rc) return rc;
+        if (lock_iters) {
+          int mx = 0;
+          for (int s = 0; s < c->nslices; ++s) mx = std::max(mx, (int)lock_iters[solve * c->nslices + s]);
+          rc = pcg_run(c, c->rhs, x, 0.0, 0, c->lock_dev + solve * c->nslices, mx, q_valid);
+        } else {
+          rc = pcg_run(c, c->rhs, x, tol, maxit, nullptr, maxit, q_valid);
+        }
+        if (rc < 0) return rc;
+        if (rc > 0) rc_all = rc;
+        if (pcg_iters)
+          for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
+        rc = enq_shrinks(c, x);
+        if (rc) return rc;
+        q_valid = false;
+      }
+      int rc = enq_outer(c, x);
+      if (rc) return rc;
+      q_valid = true;
+    }
+    if (!graph_now) {
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      return rc_all;
+    }
+    // outer iterations 2 .. n_outer from the captured graph
+    const int budget = std::min(c->graph_budget, maxit);
+    int rc = sb_graph(c, x, tol, n_inner, budget);
+    if (rc) return rc;
+    HIPCHK(c, launch_set_int(c->stream, c->solve_counter, n_inner));
+    for (int jo = 1; jo < n_outer; ++jo) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    const long long rows = nsolve * c->nslices;
+    c->hist_host.resize(2 * rows);
+    HIPCHK(c, hipMemcpyAsync(c->hist_host.data(), c->hist, sizeof(int) * rows, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hist_host.data() + rows, c->hist + c->hist_cap / 2, sizeof(int) * rows,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool over_budget = false;
+    for (long long r = (long long)n_inner * c->nslices; r < rows; ++r) {
+      const int st = c->hist_host[rows + r];
+      if (st < 0) return fail(c, st, "PCG failed inside the outer-iteration graph: %s", pics_status_string(st));
+      if (st == 0) over_budget = true;
+    }
+    if (!over_budget) {
+      if (pcg_iters)
+        for (long long r = (long long)n_inner * c->nslices; r < rows; ++r) pcg_iters[r] = c->hist_host[r];
+      return rc_all;
+    }
+    // a solve needed more than the budget: redo the reconstruction host-polled
+    int mx = 0;
+    for (long long r = (long long)n_inner * c->nslices; r < rows; ++r) mx = std::max(mx, c->hist_host[r]);
+    c->graph_budget = std::min(64, std::max(c->graph_budget * 2, mx + 2));
+    c->graph_fallbacks++;
+  }
+  return PICS_OK;
 }
 
 }  // extern "C"

@@ -132,5 +132,8 @@ int wavelet_tiles(int m, int n, int level);
 hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, const float* corr, float* kraw,
                           float* kinv, float* jac, int* bad);
 hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v);
+hipError_t launch_pcg_record(hipStream_t st, const Ws& w, int nslices, int* hist_iters, int* hist_status,
+                             int* counter);
+hipError_t launch_set_int(hipStream_t st, int* p, int v);
 
 }  // namespace pics

@@ -78,6 +78,25 @@ __global__ __launch_bounds__(256) void k_pcg_check(Ws w, double tol, int setup, 
   }
 }
 
+// Per-slice iteration count and status of the solve just finished, stored at
+// row *counter of the history; then the counter advances (graph replays).
+__global__ __launch_bounds__(256) void k_pcg_record(Ws w, int nslices, int* __restrict__ hist_iters,
+                                                    int* __restrict__ hist_status, int* __restrict__ counter) {
+  __shared__ int row;
+  if (threadIdx.x == 0) row = *counter;
+  __syncthreads();
+  for (int s = threadIdx.x; s < nslices; s += blockDim.x) {
+    hist_iters[(long long)row * nslices + s] = w.st[s].iters;
+    hist_status[(long long)row * nslices + s] = w.st[s].status;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *counter = row + 1;
+}
+
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 // ------------------------------------------------------- TV shrink/update
 // D_x x = x[i,j] - x[i-1,j], D_y x = x[i,j] - x[i,j-1] (periodic);
 // v = D x + b;  d = shrink(v, 1/lam);  b <- v - d;  u = d - b (the next
@@ -439,6 +458,17 @@ hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit,
 
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x) {
   hipLaunchKernelGGL(k_pcg_check, dim3(nslices), dim3(256), 0, st, w, tol, setup, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_record(hipStream_t st, const Ws& w, int nslices, int* hist_iters, int* hist_status,
+                             int* counter) {
+  hipLaunchKernelGGL(k_pcg_record, dim3(1), dim3(256), 0, st, w, nslices, hist_iters, hist_status, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(hipStream_t st, int* p, int v) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, p, v);
   return hipGetLastError();
 }
 

@@ -289,3 +289,41 @@ def test_split_bregman_cfg2_locked(torch, B):
     err = H.rel_err(_host(xd).reshape(spec.m, spec.n), ref.x)
     _say(f"  sb cfg2: rel err vs oracle {err:.3e}")
     assert err < 1e-3, err
+
+
+def _sb_run(torch, B, insts, budget, n_outer=8, scale_note=""):
+    ctx, ksp = _ctx(B, insts)
+    ctx.set_option(B.OPT_GRAPH_BUDGET, budget)
+    ctx.build_preconditioner("circulant")
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    iters, rc = ctx.split_bregman_recon(ksp, x, n_outer=n_outer, tol=1e-3, maxit=1000)
+    return ctx, ksp, x, iters
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e3])
+def test_split_bregman_graph_equals_host_polled(torch, B, scale):
+    """Outer iterations replayed from the captured graph give bitwise the
+    host-polled result and counts; replays are repeated with eager work and
+    synchronisations in between, and a budget too small for some solves
+    falls back to the host-polled path with the same result."""
+    _say(f"sb graph vs polled, scale {scale}")
+    specs = gen.cfg4_specs(nslices=3)
+    specs = [gen.SliceSpec(s.m, s.n, s.ncoils, s.accel, s.centre, wavelet="db4", levels=3, data_scale=scale)
+             for s in specs]
+    insts = [_inst(sp, 5000 + i) for i, sp in enumerate(specs)]
+    _, _, x_ref, it_ref = _sb_run(torch, B, insts, budget=0)
+    ref = _host(x_ref)
+    ctx, ksp, x_g, it_g = _sb_run(torch, B, insts, budget=4)
+    assert np.array_equal(it_g, it_ref)
+    assert np.array_equal(_host(x_g), ref)
+    for rep in range(3):
+        junk = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+        ctx.apply_A(junk, torch.empty_like(junk))  # eager work between replays
+        torch.cuda.synchronize()
+        x2 = torch.zeros_like(x_g)
+        it2, _ = ctx.split_bregman_recon(ksp, x2, n_outer=8, tol=1e-3, maxit=1000)
+        assert np.array_equal(it2, it_ref), rep
+        assert np.array_equal(_host(x2), ref), rep
+    _, _, x_small, it_small = _sb_run(torch, B, insts, budget=1)
+    assert np.array_equal(it_small, it_ref)
+    assert np.array_equal(_host(x_small), ref)
