@@ -265,3 +265,42 @@ def random_image(seed: int, m: int, n: int) -> np.ndarray:
 
 def to_c64(a: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.complex64)
+
+
+# ----------------------------------------------------------------------------
+# learned spectrum correction: parameter draw and training instances
+# ----------------------------------------------------------------------------
+
+# Layer list of the correction network (cin, cout, dilation); the flat
+# parameter order is W[cout][cin][3][3] then bias[cout] per layer, then the
+# 1x1 layer's w[16] and bias[1] (the layout of include/pics.h).
+NET_LAYERS = ((6, 32, 1), (32, 32, 1), (32, 32, 2), (32, 32, 4), (32, 32, 8), (32, 16, 1))
+NET_FINAL_IN = 16
+
+
+def net_param_count() -> int:
+    return sum(co * ci * 9 + co for ci, co, _ in NET_LAYERS) + NET_FINAL_IN + 1
+
+
+def net_init(seed: int) -> np.ndarray:
+    """He-normal 3x3 weights (std sqrt(2 / (9 cin))), zero biases, zero 1x1
+    weights and a 1x1 bias of ln(e - 1), so the initial correction is 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for ci, co, _ in NET_LAYERS:
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / (9 * ci)), size=co * ci * 9))
+        parts.append(np.zeros(co))
+    parts.append(np.zeros(NET_FINAL_IN))
+    parts.append(np.array([math.log(math.e - 1.0)]))
+    return np.concatenate(parts)
+
+
+def training_instances(count: int, base: int = TRAIN_SEED_BASE, m: int = 64, n: int = 64, nc: int = 4):
+    """Instances of the learned-correction training distribution (seed base
+    20000 for training, 30000 for held-out)."""
+    out = []
+    for i in range(count):
+        rng = np.random.Generator(np.random.PCG64(base + i))
+        spec = training_spec(rng, m, n, nc)
+        out.append(make_instance(spec, base + i))
+    return out
