@@ -167,6 +167,65 @@ int split_bregman_recon(pics_ctx* ctx, const void* kspace, int32_t n_outer, int3
 #define PICS_OPT_GRAPH_BUDGET 2
 int pics_set_option(pics_ctx* ctx, int32_t key, int64_t value);
 
+/* ---------------------------------------------------------------------------
+ * Learned correction of the circulant spectrum (not in the paper).
+ *
+ * A small CNN maps per-slice features to a positive correction c of k; the
+ * LEARNED preconditioner is F^H diag(1/(k c)) F.  It is trained to minimise
+ * E_z ||M_c^{-1} A z - z||^2 / E_z ||z||^2 over random probes z, which per
+ * frequency j is d_j^2 G_j - 2 d_j H_j + Z_j (d = 1/(k c)) with the probe
+ * statistics G = E|F A z|^2, H = E Re(conj(F A z) F z), Z = E|F z|^2.
+ *
+ * Network: six 3x3 convolutions with circular padding and ReLU,
+ * (cin, cout, dilation) = (6,32,1) (32,32,1) (32,32,2) (32,32,4) (32,32,8)
+ * (32,16,1), then a 1x1 convolution 16 -> 1 giving o; c = max(softplus(o),
+ * 1e-3).  Flat FP32 parameter order: per 3x3 layer W[cout][cin][3][3] then
+ * bias[cout]; then w[16], bias[1] (43105 values).  Activations bf16 on the
+ * matrix cores, FP32 weights, accumulation and optimiser state.
+ * Features: float [slice][6][64][64] on the fft-shifted 64 x 64 frequency
+ * grid (DC at (32, 32)): sampled fraction, log(coil energy / mean),
+ * log(k / mean), log10(mu/1e-3), log10(lambda/4e-3), log10(gamma/4e-3);
+ * slices must have m and n multiples of 64.
+ * ------------------------------------------------------------------------- */
+typedef struct pics_net pics_net;
+
+/* Feature planes of every slice of ctx from its masks, coil maps and the
+ * spectrum khat (image-packed float, e.g. build_preconditioner's khat_out).
+ * PICS_ERR_UNSUPPORTED if a slice's m or n is not a multiple of 64. */
+int pics_features(pics_ctx* ctx, const float* khat, float* features);
+
+/* Probe statistics G, H, Z (image-packed float, unitary DFT scaling) of A over
+ * nprobes probes (image-packed c64 each, back to back). */
+int pics_probe_stats(pics_ctx* ctx, const void* probes, int32_t nprobes, float* G, float* H, float* Z);
+
+/* Network with room for batches of up to batch_max slices; stream = hipStream_t. */
+int pics_net_create(pics_net** net, int32_t batch_max, void* stream);
+int pics_net_destroy(pics_net* net);
+int64_t pics_net_param_count(void);
+/* Host copies of the flat parameters / the last gradient. */
+int pics_net_set_params(pics_net* net, const float* params_host);
+int pics_net_get_params(pics_net* net, float* params_host);
+int pics_net_get_grad(pics_net* net, float* grad_host);
+
+/* o = network(features[index[b]]) for b < batch (index: device int32, NULL =
+ * identity); o: float [batch][64][64] on the shifted grid. */
+int pics_net_forward(pics_net* net, int32_t batch, const int32_t* index, const float* features, float* o);
+
+/* Loss (mean over the batch) and its gradient (kept in the network) for the
+ * slices index[0..batch): features [slice][6][64][64]; k, G, H, Z
+ * [slice][64][64] (unshifted).  Synchronises the stream; loss_host optional. */
+int pics_net_loss_grad(pics_net* net, int32_t batch, const int32_t* index, const float* features, const float* k,
+                       const float* G, const float* H, const float* Z, double* loss_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradient. */
+int pics_net_adam_step(pics_net* net, float lr);
+
+/* Correction map c for every slice of ctx (image-packed float), from the
+ * slice features: network output interpolated periodically-bilinearly from
+ * the 64 x 64 shifted grid to m x n, unshifted.  Feed it to
+ * build_preconditioner(PICS_PRECOND_LEARNED). */
+int pics_net_correction(pics_net* net, pics_ctx* ctx, const float* features, float* correction);
+
 const char* pics_status_string(int status);
 const char* pics_last_error(const pics_ctx* ctx);
 

@@ -43,7 +43,10 @@ _LIB = None
 
 EXPORTS = ["pics_create", "pics_destroy", "pics_sizes", "build_preconditioner", "apply_A", "apply_Minv",
            "pics_fft2", "pics_wavelet", "pcg_solve", "split_bregman_recon", "pics_set_option",
-           "pics_status_string", "pics_last_error"]
+           "pics_status_string", "pics_last_error", "pics_features", "pics_probe_stats", "pics_net_create",
+           "pics_net_destroy", "pics_net_param_count", "pics_net_set_params", "pics_net_get_params",
+           "pics_net_get_grad", "pics_net_forward", "pics_net_loss_grad", "pics_net_adam_step",
+           "pics_net_correction"]
 
 
 def lib(path: str = LIB_PATH):
@@ -70,6 +73,18 @@ def lib(path: str = LIB_PATH):
         "pics_set_option": (ctypes.c_int, [vp, i32, i64]),
         "pics_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pics_last_error": (ctypes.c_char_p, [vp]),
+        "pics_features": (ctypes.c_int, [vp, vp, vp]),
+        "pics_probe_stats": (ctypes.c_int, [vp, vp, i32, vp, vp, vp]),
+        "pics_net_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, vp]),
+        "pics_net_destroy": (ctypes.c_int, [vp]),
+        "pics_net_param_count": (i64, []),
+        "pics_net_set_params": (ctypes.c_int, [vp, vp]),
+        "pics_net_get_params": (ctypes.c_int, [vp, vp]),
+        "pics_net_get_grad": (ctypes.c_int, [vp, vp]),
+        "pics_net_forward": (ctypes.c_int, [vp, i32, vp, vp, vp]),
+        "pics_net_loss_grad": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, pdbl]),
+        "pics_net_adam_step": (ctypes.c_int, [vp, ctypes.c_float]),
+        "pics_net_correction": (ctypes.c_int, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -177,6 +192,76 @@ class Context:
                                         iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         self._check(rc)
         return iters, rc
+
+    def features(self, khat, out):
+        """Feature planes [nslices][6][64][64] (float32 device tensor `out`)."""
+        return self._check(self.L.pics_features(self.h, _ptr(khat), _ptr(out)))
+
+    def probe_stats(self, probes, nprobes: int, G, H, Z):
+        return self._check(self.L.pics_probe_stats(self.h, _ptr(probes), int(nprobes), _ptr(G), _ptr(H), _ptr(Z)))
+
+
+class Net:
+    """The spectrum-correction network of libpics (parameters on the device)."""
+
+    def __init__(self, batch_max: int, stream=None):
+        import torch
+        self.L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        rc = self.L.pics_net_create(ctypes.byref(h), int(batch_max), ctypes.c_void_p(stream))
+        if rc != PICS_OK:
+            raise PicsError(rc, self.L.pics_status_string(rc).decode())
+        self.h = h
+        self.batch_max = batch_max
+        self.count = int(self.L.pics_net_param_count())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pics_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise PicsError(rc, self.L.pics_status_string(rc).decode())
+        return rc
+
+    def set_params(self, theta: np.ndarray):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        assert t.size == self.count
+        return self._check(self.L.pics_net_set_params(self.h, t.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self) -> np.ndarray:
+        t = np.empty(self.count, np.float32)
+        self._check(self.L.pics_net_get_params(self.h, t.ctypes.data_as(ctypes.c_void_p)))
+        return t
+
+    def get_grad(self) -> np.ndarray:
+        t = np.empty(self.count, np.float32)
+        self._check(self.L.pics_net_get_grad(self.h, t.ctypes.data_as(ctypes.c_void_p)))
+        return t
+
+    def forward(self, batch: int, features, out, index=None):
+        return self._check(self.L.pics_net_forward(self.h, int(batch), _ptr(index), _ptr(features), _ptr(out)))
+
+    def loss_grad(self, batch: int, index, features, k, G, H, Z) -> float:
+        loss = ctypes.c_double()
+        self._check(self.L.pics_net_loss_grad(self.h, int(batch), _ptr(index), _ptr(features), _ptr(k), _ptr(G),
+                                              _ptr(H), _ptr(Z), ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr: float):
+        return self._check(self.L.pics_net_adam_step(self.h, ctypes.c_float(lr)))
+
+    def correction(self, ctx: "Context", features, out):
+        return self._check(self.L.pics_net_correction(self.h, ctx.h, _ptr(features), _ptr(out)))
 
 
 # ---------------------------------------------------------------------------

@@ -12,6 +12,7 @@
 #include "../../include/pics.h"
 #include "fft.hpp"
 #include "internal.hpp"
+#include "learned.hpp"
 
 using namespace pics;
 
@@ -43,7 +44,7 @@ struct pics_ctx {
   float2* tw = nullptr;
   float2 *r, *t, *z, *p, *pn, *q, *g1, *g, *rhs, *bx, *by, *bw, *ux, *uy, *uw, *w1, *w2;
   float2* coiltmp = nullptr;
-  float *kraw, *kinv, *jac;
+  float *kraw, *kinv, *jac, *ftmp;
   double *part, *pbar;
   PcgState* st = nullptr;
   int* bad = nullptr;
@@ -322,6 +323,7 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   add((void**)&c->kraw, sizeof(float) * I);
   add((void**)&c->kinv, sizeof(float) * I);
   add((void**)&c->jac, sizeof(float) * I);
+  add((void**)&c->ftmp, sizeof(float) * I);
   add((void**)&c->part, sizeof(double) * nslices * kSlots * kPartMax);
   add((void**)&c->pbar, sizeof(double) * std::max(1LL, c->aux_total));
   add((void**)&c->st, sizeof(PcgState) * nslices);
@@ -789,6 +791,260 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
     c->graph_budget = std::min(64, std::max(c->graph_budget * 2, mx + 2));
     c->graph_fallbacks++;
   }
+  return PICS_OK;
+}
+
+}  // extern "C"
+
+// =================================================================== learned
+namespace {
+const int kLayerSpec[kNetLayers][3] = {{6, 32, 1}, {32, 32, 1}, {32, 32, 2}, {32, 32, 4}, {32, 32, 8}, {32, 16, 1}};
+}
+
+struct pics_net {
+  hipStream_t stream = nullptr;
+  int bmax = 0;
+  void* block = nullptr;
+  NetLayout L{};
+  float *theta, *grad, *m, *v;
+  uint16_t* act[kNetLayers + 1];
+  uint16_t* gbuf[2];
+  float *o, *go, *part;
+  double *loss_part, *zsum;
+  double* loss_host = nullptr;  // pinned
+  int t = 0;
+  bool prepped = false;
+  std::string err;
+};
+
+namespace {
+int nfail(pics_net* n, int code, const char* msg) {
+  if (n) n->err = msg;
+  return code;
+}
+#define NETCHK(net, expr)                                              \
+  do {                                                                 \
+    hipError_t e_ = (expr);                                            \
+    if (e_ != hipSuccess) return nfail(net, PICS_ERR_HIP, hipGetErrorString(e_)); \
+  } while (0)
+
+int net_prep(pics_net* n) {
+  if (!n->prepped) {
+    NETCHK(n, launch_net_prep(n->stream, n->theta, n->L));
+    n->prepped = true;
+  }
+  return PICS_OK;
+}
+
+int net_forward(pics_net* n, int batch, const int* index, const float* feat) {
+  int rc = net_prep(n);
+  if (rc) return rc;
+  NETCHK(n, launch_net_input(n->stream, feat, index, batch, n->act[0]));
+  for (int l = 0; l < kNetLayers; ++l) {
+    const NetLayer& ly = n->L.layer[l];
+    NETCHK(n, launch_conv_fwd(n->stream, ly.cinp, ly.cout, n->act[l], ly.wf, n->theta + ly.woff + ly.cout * ly.cin * 9,
+                              ly.dil, batch, n->act[l + 1]));
+  }
+  return PICS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t pics_net_param_count(void) {
+  long long c = 0;
+  for (int l = 0; l < kNetLayers; ++l) c += (long long)kLayerSpec[l][1] * kLayerSpec[l][0] * 9 + kLayerSpec[l][1];
+  return c + 17;
+}
+
+int pics_net_create(pics_net** out, int32_t batch_max, void* stream) {
+  if (!out || batch_max < 1 || batch_max > 4096) return PICS_ERR_INVALID;
+  *out = nullptr;
+  pics_net* n = new pics_net();
+  n->stream = (hipStream_t)stream;
+  n->bmax = batch_max;
+  long long off = 0;
+  for (int l = 0; l < kNetLayers; ++l) {
+    NetLayer& ly = n->L.layer[l];
+    ly.cin = kLayerSpec[l][0];
+    ly.cout = kLayerSpec[l][1];
+    ly.dil = kLayerSpec[l][2];
+    ly.cinp = ly.cin <= 16 ? 16 : 32;
+    ly.woff = off;
+    off += (long long)ly.cout * ly.cin * 9 + ly.cout;
+  }
+  n->L.final_off = off;
+  n->L.count = off + 17;
+  const long long P = n->L.count;
+  const long long cells = (long long)kNetGrid * kNetGrid;
+  std::vector<std::pair<void**, size_t>> plan;
+  auto add = [&](void** p, size_t bytes) { plan.push_back({p, (bytes + 255) / 256 * 256}); };
+  add((void**)&n->theta, sizeof(float) * P);
+  add((void**)&n->grad, sizeof(float) * P);
+  add((void**)&n->m, sizeof(float) * P);
+  add((void**)&n->v, sizeof(float) * P);
+  for (int l = 0; l < kNetLayers; ++l) {
+    NetLayer& ly = n->L.layer[l];
+    add((void**)&ly.wf, sizeof(uint16_t) * ly.cout * 9 * ly.cinp);
+    add((void**)&ly.wb, sizeof(uint16_t) * ly.cout * 9 * ly.cinp);
+  }
+  add((void**)&n->act[0], sizeof(uint16_t) * batch_max * cells * 16);
+  for (int l = 0; l < kNetLayers; ++l)
+    add((void**)&n->act[l + 1], sizeof(uint16_t) * batch_max * cells * n->L.layer[l].cout);
+  for (int i = 0; i < 2; ++i) add((void**)&n->gbuf[i], sizeof(uint16_t) * batch_max * cells * 32);
+  add((void**)&n->o, sizeof(float) * batch_max * cells);
+  add((void**)&n->go, sizeof(float) * batch_max * cells);
+  add((void**)&n->part, sizeof(float) * batch_max * kNetGrid * (32 * 32 * 9 + 32));
+  add((void**)&n->loss_part, sizeof(double) * batch_max * kNetGrid);
+  add((void**)&n->zsum, sizeof(double) * batch_max);
+  size_t total = 0;
+  for (auto& pr : plan) total += pr.second;
+  if (hipMalloc(&n->block, total) != hipSuccess) {
+    delete n;
+    return PICS_ERR_HIP;
+  }
+  char* base = (char*)n->block;
+  for (auto& pr : plan) {
+    *pr.first = base;
+    base += pr.second;
+  }
+  if (hipHostMalloc((void**)&n->loss_host, sizeof(double) * batch_max * kNetGrid, hipHostMallocDefault) != hipSuccess ||
+      hipMemset(n->block, 0, total) != hipSuccess) {
+    if (n->loss_host) hipHostFree(n->loss_host);
+    hipFree(n->block);
+    delete n;
+    return PICS_ERR_HIP;
+  }
+  *out = n;
+  return PICS_OK;
+}
+
+int pics_net_destroy(pics_net* n) {
+  if (!n) return PICS_ERR_INVALID;
+  hipStreamSynchronize(n->stream);
+  if (n->loss_host) hipHostFree(n->loss_host);
+  if (n->block) hipFree(n->block);
+  delete n;
+  return PICS_OK;
+}
+
+int pics_net_set_params(pics_net* n, const float* params) {
+  if (!n || !params) return PICS_ERR_INVALID;
+  NETCHK(n, hipMemcpyAsync(n->theta, params, sizeof(float) * n->L.count, hipMemcpyHostToDevice, n->stream));
+  NETCHK(n, hipMemsetAsync(n->m, 0, sizeof(float) * n->L.count, n->stream));
+  NETCHK(n, hipMemsetAsync(n->v, 0, sizeof(float) * n->L.count, n->stream));
+  NETCHK(n, hipStreamSynchronize(n->stream));
+  n->t = 0;
+  n->prepped = false;
+  return PICS_OK;
+}
+
+int pics_net_get_params(pics_net* n, float* params) {
+  if (!n || !params) return PICS_ERR_INVALID;
+  NETCHK(n, hipMemcpyAsync(params, n->theta, sizeof(float) * n->L.count, hipMemcpyDeviceToHost, n->stream));
+  NETCHK(n, hipStreamSynchronize(n->stream));
+  return PICS_OK;
+}
+
+int pics_net_get_grad(pics_net* n, float* g) {
+  if (!n || !g) return PICS_ERR_INVALID;
+  NETCHK(n, hipMemcpyAsync(g, n->grad, sizeof(float) * n->L.count, hipMemcpyDeviceToHost, n->stream));
+  NETCHK(n, hipStreamSynchronize(n->stream));
+  return PICS_OK;
+}
+
+int pics_net_forward(pics_net* n, int32_t batch, const int32_t* index, const float* feat, float* o) {
+  if (!n || !feat || !o || batch < 1 || batch > n->bmax) return PICS_ERR_INVALID;
+  int rc = net_forward(n, batch, index, feat);
+  if (rc) return rc;
+  NETCHK(n, launch_net_head(n->stream, n->act[kNetLayers], n->theta, (int)n->L.final_off, index, batch, nullptr,
+                            nullptr, nullptr, nullptr, nullptr, o, nullptr, n->loss_part));
+  return PICS_OK;
+}
+
+int pics_net_loss_grad(pics_net* n, int32_t batch, const int32_t* index, const float* feat, const float* k,
+                       const float* G, const float* H, const float* Z, double* loss_host) {
+  if (!n || !feat || !k || !G || !H || !Z || batch < 1 || batch > n->bmax) return PICS_ERR_INVALID;
+  if (!index) return nfail(n, PICS_ERR_INVALID, "loss_grad needs a device index array");
+  int rc = net_forward(n, batch, index, feat);
+  if (rc) return rc;
+  // zsum[b] = sum_j Z_j of slice index[b]
+  NETCHK(n, launch_plane_sums_indexed(n->stream, Z, index, batch, n->zsum));
+  NETCHK(n, launch_net_head(n->stream, n->act[kNetLayers], n->theta, (int)n->L.final_off, index, batch, k, G, H, Z,
+                            n->zsum, n->o, n->go, n->loss_part));
+  // backward
+  const long long rows = (long long)batch * kNetGrid;
+  NETCHK(n, launch_net_head_bwd(n->stream, n->act[kNetLayers], n->theta, (int)n->L.final_off, n->go, batch, n->gbuf[0],
+                                n->part));
+  NETCHK(n, launch_reduce_rows(n->stream, n->part, (int)rows, 17, n->grad + n->L.final_off));
+  int cur = 0;
+  for (int l = kNetLayers - 1; l >= 0; --l) {
+    const NetLayer& ly = n->L.layer[l];
+    const int count = ly.cout * ly.cin * 9 + ly.cout;
+    NETCHK(n, launch_conv_bwd_w(n->stream, ly.cinp, ly.cin, ly.cout, n->act[l], n->gbuf[cur], ly.dil, batch, n->part));
+    NETCHK(n, launch_reduce_rows(n->stream, n->part, (int)rows, count, n->grad + ly.woff));
+    if (l > 0) {
+      NETCHK(n, launch_conv_bwd_data(n->stream, ly.cinp, ly.cout, n->gbuf[cur], ly.wb, n->act[l], ly.dil, batch,
+                                     n->gbuf[1 - cur]));
+      cur = 1 - cur;
+    }
+  }
+  NETCHK(n, hipMemcpyAsync(n->loss_host, n->loss_part, sizeof(double) * rows, hipMemcpyDeviceToHost, n->stream));
+  NETCHK(n, hipStreamSynchronize(n->stream));
+  if (loss_host) {
+    double acc = 0.0;
+    for (long long r = 0; r < rows; ++r) acc += n->loss_host[r];
+    *loss_host = acc / batch;
+  }
+  return PICS_OK;
+}
+
+int pics_net_adam_step(pics_net* n, float lr) {
+  if (!n || !(lr > 0.f)) return PICS_ERR_INVALID;
+  n->t++;
+  NETCHK(n, launch_adam(n->stream, n->theta, n->grad, n->m, n->v, (int)n->L.count, lr, n->t));
+  n->prepped = false;
+  return PICS_OK;
+}
+
+int pics_features(pics_ctx* c, const float* khat, float* features) {
+  if (!c || !khat || !features) return PICS_ERR_INVALID;
+  for (const SliceDev& sd : c->sl)
+    if (sd.m % kNetGrid || sd.n % kNetGrid) return fail(c, PICS_ERR_UNSUPPORTED, "features need m, n multiples of 64");
+  for (auto& g : c->groups)
+    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 2, c->sens, c->coiltmp));
+  for (auto& g : c->groups) HIPCHK(c, launch_col_coil_energy(make_launch(c, g), ws_for(c, g), c->coiltmp, c->ftmp));
+  HIPCHK(c, launch_features(c->stream, make_ws(c), c->nslices, c->ftmp, khat, features));
+  return PICS_OK;
+}
+
+int pics_probe_stats(pics_ctx* c, const void* probes, int32_t nprobes, float* G, float* H, float* Z) {
+  if (!c || !probes || nprobes < 1 || !G || !H || !Z) return PICS_ERR_INVALID;
+  const float2* pr = (const float2*)probes;
+  for (int p = 0; p < nprobes; ++p) {
+    const float2* z = pr + (long long)p * c->img_total;
+    int rc = apply_A(c, z, c->w1, PICS_TERM_ALL);
+    if (rc) return rc;
+    rc = pics_fft2(c, c->w1, c->w1, 0);
+    if (rc) return rc;
+    rc = pics_fft2(c, z, c->w2, 0);
+    if (rc) return rc;
+    HIPCHK(c, launch_probe_accum(make_simple(c), make_ws(c), c->w1, c->w2, G, H, Z, 1.0f / nprobes, p == 0));
+  }
+  return PICS_OK;
+}
+
+int pics_net_correction(pics_net* n, pics_ctx* c, const float* features, float* corr) {
+  if (!n || !c || !features || !corr) return PICS_ERR_INVALID;
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // features come from the context's stream
+  const long long cells = (long long)kNetGrid * kNetGrid;
+  for (int s0 = 0; s0 < c->nslices; s0 += n->bmax) {
+    const int b = std::min(n->bmax, c->nslices - s0);
+    int rc = pics_net_forward(n, b, nullptr, features + (long long)s0 * kNetFeat * cells, n->o);
+    if (rc) return fail(c, rc, n->err.c_str());
+    HIPCHK(c, launch_net_upsample(n->stream, make_ws(c), n->o, s0, b, c->max_pixels, corr));
+  }
+  HIPCHK(c, hipStreamSynchronize(n->stream));
   return PICS_OK;
 }
 

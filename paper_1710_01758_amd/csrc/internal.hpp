@@ -117,6 +117,7 @@ hipError_t launch_col_fft(const Launch& L, const Ws& w, int inverse, const float
 hipError_t launch_col_sb_init(const Launch& L, const Ws& w, const float2* coil_rows, float2* g1, float2* g,
                               float2* x);
 hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, float* energy);
+hipError_t launch_col_coil_energy(const Launch& L, const Ws& w, const float2* coil_rows, float* energy);
 
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit, const int* maxit_per_slice);

@@ -425,8 +425,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_z(Ws w, const float2
 }
 
 // ----------------------------------------------------------------------------
-// Plain row FFT (unnormalised).  ncoil_mode: loop over the slice's coils on
-// coil-shaped buffers, zeroing unsampled k-space first (R y before F^H).
+// Plain row FFT (unnormalised).  ncoil_mode 1: loop over the slice's coils on
+// coil-shaped buffers, zeroing unsampled k-space first (R y before F^H);
+// ncoil_mode 2: the same loop without the mask.
 // ----------------------------------------------------------------------------
 template <int N, int DIR>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_mode, const float2* __restrict__ in,
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
     for (int e = 0; e < E; ++e) {
       float2 a = in[rowbase + t + NT * e];
       if (ncoil_mode) {
-        const bool keep = sd.mask_kind == 0 ? mk[i] != 0 : mk[(long long)i * N + t + NT * e] != 0;
+        const bool keep = ncoil_mode == 2 || (sd.mask_kind == 0 ? mk[i] != 0 : mk[(long long)i * N + t + NT * e] != 0);
         if (!keep) a = make_float2(0.f, 0.f);
       }
       v[e] = a;
@@ -580,6 +581,40 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, dou
     for (int off = T / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
     if (j == 0) pbar[sd.aux + (long long)blockIdx.x * M + (t + NT * e)] = a;
   }
+}
+
+// ----------------------------------------------------------------------------
+// Unitary k-space coil energy sum_c |F s_c|^2 per pixel: the column pass of the
+// 2D transform of every coil map (the row pass already ran), squared
+// magnitudes summed over coils, scaled by 1 / N.
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, const float2* __restrict__ coil_rows,
+                                                                        float* __restrict__ energy) {
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  __shared__ float2 lds[M * T];
+  __shared__ float2 s_tw[M];
+  const int s = w.group[blockIdx.y];
+  const SliceDev sd = w.sl[s];
+  const int n = sd.n;
+  const int j = threadIdx.x % T, t = threadIdx.x / T;
+  const int col = blockIdx.x * T + j;
+  stage_twiddles<M, ColCfg<M>::THREADS>(s_tw, w.tw);
+  float en[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) en[e] = 0.f;
+  for (int c = 0; c < sd.nc; ++c) {
+    const long long cb = sd.coil + (long long)c * M * n;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = coil_rows[cb + (long long)(t + NT * e) * n + col];
+    fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) en[e] += cabs2(v[e]);
+  }
+  const float inv = 1.0f / ((float)M * (float)n);
+#pragma unroll
+  for (int e = 0; e < E; ++e) energy[sd.img + (long long)(t + NT * e) * n + col] = en[e] * inv;
 }
 
 // ============================================================== launchers
@@ -719,6 +754,21 @@ hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, flo
 #define PICS_CASE(M)                                                                                           \
   case M:                                                                                                      \
     hipLaunchKernelGGL(k_col_coil_power<M>, grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, pbar, energy); \
+    break;
+    PICS_FFT_SIZES(PICS_CASE)
+#undef PICS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_col_coil_energy(const Launch& L, const Ws& w, const float2* coil_rows, float* energy) {
+  const dim3 grid(L.n / kColT, L.count);
+  switch (L.m) {
+#define PICS_CASE(M)                                                                                               \
+  case M:                                                                                                          \
+    hipLaunchKernelGGL(k_col_coil_energy<M>, grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, coil_rows, energy); \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE
