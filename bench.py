@@ -123,6 +123,48 @@ def cpu_baseline(inst, min_seconds=10.0):
                       f"256x256x12 slice in FP64 NumPy with single-threaded pocketfft, {dt:.1f} s"}
 
 
+def learned_section(torch, B, steps):
+    """Train the spectrum correction on 2000 instances of the 64 x 64 x 4
+    training distribution (random R in [2, 8], mu / lambda / gamma within a
+    decade), report held-out losses (200 instances) and compare circulant with
+    learned on the 256 x 256 x 12 slice: Split Bregman per-solve PCG counts and
+    a PCG solve of A x = A x_true from 0 (iterations to 1e-3, relative residual
+    after 0..3 iterations)."""
+    from paper_1710_01758_amd import learned as LD
+    t0 = time.perf_counter()
+    log("bench: learned - building datasets")
+    train = LD.build_dataset(gen.training_instances(2000, base=gen.TRAIN_SEED_BASE), nprobes=8)
+    held = LD.build_dataset(gen.training_instances(200, base=gen.HELDOUT_SEED_BASE), nprobes=8, probe_seed=95_000)
+    net = B.Net(16)
+    net.set_params(gen.net_init(20_260).astype(np.float32))
+    circ = LD.dataset_loss(net, held)
+    t1 = time.perf_counter()
+    losses = LD.train(net, train, steps=steps, batch=16, lr=1e-3, log_every=500, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    learned = LD.dataset_loss(net, held)
+    floor = LD.superoptimal_loss(held)
+    inst = gen.make_instance(gen.CFG5, gen.eval_seed(5))
+    sb = LD.evaluate_on(inst, net, n_outer=20)
+    pcg = LD.pcg_first_solve(inst, net, curve=3)
+    inst_s = gen.make_instance(gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1e3),
+                               gen.eval_seed(5))
+    sb_scaled = LD.evaluate_on(inst_s, net, n_outer=20)
+    ceiling = LD.evaluate_correction(inst, LD.superoptimal_correction(inst, nprobes=32))
+    for d in (train, held):
+        d.ctx.close()
+    net.close()
+    return {
+        "train": {"instances": 2000, "steps": steps, "batch": 16, "lr": 1e-3, "seconds": round(t_train, 2),
+                  "loss_first_50": float(np.mean(losses[:50])), "loss_last_50": float(np.mean(losses[-50:]))},
+        "heldout_loss": {"circulant": circ, "learned": learned, "superoptimal_floor": floor,
+                         "gap_closed": (circ - learned) / (circ - floor) if circ > floor else None},
+        "slice_256x256x12": {"split_bregman": sb, "pcg_from_zero": pcg, "split_bregman_data_scale_1e3": sb_scaled,
+                             "superoptimal_probe_ceiling": ceiling},
+        "seconds_total": round(time.perf_counter() - t0, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +173,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="slices reconstructed per step")
     ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip training / evaluating the learned correction")
+    ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--mode", choices=["full", "apply"], default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs)")
     a = ap.parse_args()
@@ -226,6 +270,8 @@ def main():
                      "kernel": "k_col_apply<256, 0> (fused apply_A, 32 slices per launch)",
                      "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": bytes_apply},
     }
+    if not a.no_learned:
+        out["learned"] = learned_section(torch, B, a.train_steps)
     if not a.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(insts[0])

@@ -99,3 +99,101 @@ def correction_for(net: "B.Net", ctx: "B.Context", khat) -> object:
     corr = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
     net.correction(ctx, feats, corr)
     return corr
+
+
+def relres_curve(ctx: "B.Context", b, x0, iters: int) -> List[float]:
+    """Recursive relative residual after 0 .. iters PCG iterations (one
+    iteration-locked solve per count, from the same start)."""
+    import torch
+    out = []
+    for k in range(iters + 1):
+        x = x0.clone()
+        _, rel, _, _ = ctx.pcg_solve(b, x, 0.0, 0, maxit_per_slice=[k] * ctx.n)
+        out.append(float(rel[0]))
+    return out
+
+
+def evaluate_on(instance, net: Optional["B.Net"], n_outer: int = 20, curve: int = 3) -> dict:
+    """PCG and Split Bregman iteration counts of one slice with the circulant
+    preconditioner and (if a network is given) the learned one."""
+    import torch
+    ctx, ksp = B.context_for([instance])
+    s = instance.spec
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    corr = correction_for(net, ctx, khat) if net is not None else None
+    res = {}
+    kinds = ["circulant"] + (["learned"] if net is not None else [])
+    for kind in kinds:
+        rc = ctx.build_preconditioner(kind, correction=corr if kind == "learned" else None)
+        x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+        it, _ = ctx.split_bregman_recon(ksp, x, n_outer=n_outer, tol=1e-3, maxit=1000)
+        r = {"sb_pcg_iters": it[:, 0].tolist(), "sb_total": int(it[:, 0].sum()), "build_rc": int(rc)}
+        res[kind] = r
+    if corr is not None:
+        c = corr.cpu().numpy()
+        res["correction_range"] = [float(c.min()), float(c.max())]
+    ctx.close()
+    return res
+
+
+def pcg_first_solve(instance, net: Optional["B.Net"], curve: int = 3) -> dict:
+    """PCG on A x = b with b = A x_true from x0 = 0: iterations to 1e-3 and
+    the relative residual after 0..curve iterations, per preconditioner."""
+    import torch
+    ctx, ksp = B.context_for([instance])
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    corr = correction_for(net, ctx, khat) if net is not None else None
+    # right-hand side b = A x_true (x_true: the phantom)
+    xt = B.to_device(instance.x_true.astype(np.complex64).ravel())
+    b = torch.empty_like(xt)
+    ctx.apply_A(xt, b, B.TERM_ALL)
+    out = {}
+    for kind in ["none", "circulant"] + (["learned"] if net is not None else []):
+        ctx.build_preconditioner(kind, correction=corr if kind == "learned" else None)
+        x0 = torch.zeros_like(b)
+        x = x0.clone()
+        it, rel, st, _ = ctx.pcg_solve(b, x, 1e-3, 1000)
+        out[kind] = {"iters_to_1e-3": int(it[0]), "relres_curve": relres_curve(ctx, b, x0, curve)}
+    ctx.close()
+    return out
+
+
+def superoptimal_correction(instance, nprobes: int = 32, probe_seed: int = 97_000):
+    """Probe estimate of the per-frequency optimum c* = G / (k H) of the loss
+    at the slice's own resolution (the ceiling of any spectrum correction)."""
+    import torch
+    ctx, _ = B.context_for([instance])
+    s = instance.spec
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    probes = np.stack([gen.probe_vectors(probe_seed + p, 1, s.m, s.n)[0].ravel() for p in range(nprobes)])
+    pd = B.to_device(probes.astype(np.complex64).ravel())
+    G = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    H = torch.empty_like(G)
+    Z = torch.empty_like(G)
+    ctx.probe_stats(pd, nprobes, G, H, Z)
+    c = (G.double() / (khat.double() * H.double())).float()
+    ctx.close()
+    return c
+
+
+def evaluate_correction(instance, corr, n_outer: int = 20, curve: int = 3) -> dict:
+    """Split Bregman counts and a PCG residual curve with a given correction."""
+    import torch
+    ctx, ksp = B.context_for([instance])
+    rc = ctx.build_preconditioner("learned", correction=corr)
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    it, _ = ctx.split_bregman_recon(ksp, x, n_outer=n_outer, tol=1e-3, maxit=1000)
+    xt = B.to_device(instance.x_true.astype(np.complex64).ravel())
+    b = torch.empty_like(xt)
+    ctx.apply_A(xt, b, B.TERM_ALL)
+    x0 = torch.zeros_like(b)
+    xx = x0.clone()
+    itp, _, _, _ = ctx.pcg_solve(b, xx, 1e-3, 1000)
+    out = {"sb_pcg_iters": it[:, 0].tolist(), "sb_total": int(it[:, 0].sum()), "build_rc": int(rc),
+           "pcg_iters_to_1e-3": int(itp[0]), "relres_curve": relres_curve(ctx, b, x0, curve),
+           "correction_range": [float(corr.min()), float(corr.max())]}
+    ctx.close()
+    return out
