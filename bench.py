@@ -123,6 +123,36 @@ def cpu_baseline(inst, min_seconds=10.0):
                       f"256x256x12 slice in FP64 NumPy with single-threaded pocketfft, {dt:.1f} s"}
 
 
+def workload_section(torch, B, insts, label, steps=2):
+    """Reconstructions per second and the apply_A roofline for another batch."""
+    ctx, ksp = B.context_for(insts)
+    split = ctx.autotune()
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+
+    def run():
+        ctx.build_preconditioner("circulant")
+        return ctx.split_bregman_recon(ksp, x, n_outer=20, tol=1e-3, maxit=1000)[0]
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        it = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    xa = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    ya = torch.empty_like(xa)
+    t_apply = time_apply_kernel(torch, ctx, xa, ya, reps=20)
+    byts = apply_bytes([i.spec for i in insts])
+    ctx.close()
+    return {"workload": label, "slices": len(insts), "recons_per_s": round(len(insts) / dt, 2),
+            "ms_per_batch": round(dt * 1e3, 3), "pcg_iters_total": int(it.sum()), "coil_split": split,
+            "pcg_iters_first_solve_max": int(it[0].max()),
+            "apply_roofline": {"bound": "hbm", "achieved": round(byts / t_apply / 1e9, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(byts / t_apply / 1e9 / HBM_PEAK_GBS, 4),
+                               "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": byts}}
+
+
 def learned_section(torch, B, steps):
     """Train the spectrum correction on 2000 instances of the 64 x 64 x 4
     training distribution (random R in [2, 8], mu / lambda / gamma within a
@@ -174,6 +204,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip training / evaluating the learned correction")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 512^2 x 32 slice and the ragged batch")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--mode", choices=["full", "apply"], default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs)")
@@ -193,6 +224,7 @@ def main():
     if a.mode == "apply":
         run_apply_mode(torch, ctx, insts)
         return
+    split = ctx.autotune()
     x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
     torch.cuda.synchronize()
 
@@ -217,6 +249,7 @@ def main():
 
     # single-slice latency (one reconstruction alone)
     ctx1, ksp1 = B.context_for(insts[:1])
+    split1 = ctx1.autotune()
     x1 = torch.zeros(ctx1.image_elems, dtype=torch.complex64, device="cuda")
     for _ in range(2):
         ctx1.build_preconditioner("circulant")
@@ -259,6 +292,7 @@ def main():
                                f"batch of {a.batch} slices per step, data_scale {a.scale:g}",
                    "global_batch": a.batch, "m": 256, "n": 256, "ncoils": 12, "parallelism": "none (1 GPU)"},
         "single_slice_recons_per_s": round(single, 3),
+        "coil_split": {"batch": split[0], "single_slice": split1[0]},
         "pcg_iters": {
             "none": {"first_solve": int(it_none[0, 0]), "total_20_solves": int(it_none[:, 0].sum()),
                      "per_solve": it_none[:, 0].tolist()},
@@ -267,9 +301,20 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_col_apply<256, 0> (fused apply_A, 32 slices per launch)",
+                     "kernel": (f"k_col_apply<256, 0, 0> (fused apply_A, {a.batch} slices per launch)" if split[0] == 1
+                                else f"k_col_apply<256, 0, 1> + <256, 0, 2> (apply_A, coil split {split[0]})"),
                      "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": bytes_apply},
     }
+    if not a.no_extra:
+        log("bench: 512x512x32 slice")
+        out["slice_512x512x32"] = workload_section(
+            torch, B, [gen.make_instance(gen.CFG3, gen.eval_seed(3))],
+            "512x512, 32 coils, variable-density lines R=6 (32 centre), TV + db4 x4")
+        log("bench: ragged batch of 64 slices")
+        specs = gen.cfg4_specs()
+        out["ragged_batch_64"] = workload_section(
+            torch, B, [gen.make_instance(sp, gen.eval_seed(4, i)) for i, sp in enumerate(specs)],
+            "64 slices {128^2, 192^2, 256x224, 320^2}, 8-32 coils, R in {3,4,6}, TV + db4 x3")
     if not a.no_learned:
         out["learned"] = learned_section(torch, B, a.train_steps)
     if not a.no_cpu_baseline:

@@ -72,6 +72,8 @@ extern "C" {
 #define PICS_TERM_TV 2           /* lambda (D_x^H D_x + D_y^H D_y), periodic backward differences */
 #define PICS_TERM_GAMMA 4        /* gamma W^H W = gamma I (W unitary) */
 #define PICS_TERM_ALL 7
+#define PICS_TERM_WAVELET_EXPLICIT 8 /* with PICS_TERM_GAMMA: evaluate gamma W^H W x through the wavelet
+                                        analysis and synthesis instead of gamma x (apply_A only) */
 
 /* One slice.  m, n in {64, 128, 192, 224, 256, 320, 512}; ncoils >= 1;
  * levels: wavelet levels (each level needs even extents); mu, lambda,
@@ -112,7 +114,8 @@ int pics_sizes(const pics_ctx* ctx, int64_t* image_elems, int64_t* coil_elems, i
  * circulant k with PICS_WARN_FALLBACK. */
 int build_preconditioner(pics_ctx* ctx, int32_t kind, const float* correction, float* khat_out);
 
-/* y = A x for every slice (Eq. system); terms selects PICS_TERM_* parts.
+/* y = A x for every slice (Eq. system); terms selects PICS_TERM_* parts
+ * (PICS_TERM_WAVELET_EXPLICIT routes the gamma term through W and W^H).
  * x and y image-packed c64, must not alias. */
 int apply_A(pics_ctx* ctx, const void* x, void* y, int32_t terms);
 
@@ -162,9 +165,13 @@ int split_bregman_recon(pics_ctx* ctx, const void* kspace, int32_t n_outer, int3
  *   solves carry this many iterations (kernels of converged slices exit at
  *   entry).  If a solve needs more, the reconstruction is redone host-polled,
  *   so results never depend on the budget; the budget is then raised.
- *   0 disables the graph.  Default 2. */
+ *   0 disables the graph.  Default 2.
+ * PICS_OPT_COIL_GROUPS: split every column tile's coil loop over this many
+ *   workgroups (clamped to each group's coil count), overriding the
+ *   autotuner; 1 = no split (the default before pics_autotune). */
 #define PICS_OPT_POLL_CHUNK 1
 #define PICS_OPT_GRAPH_BUDGET 2
+#define PICS_OPT_COIL_GROUPS 3
 int pics_set_option(pics_ctx* ctx, int32_t key, int64_t value);
 
 /* ---------------------------------------------------------------------------
@@ -225,6 +232,22 @@ int pics_net_adam_step(pics_net* net, float lr);
  * the 64 x 64 shifted grid to m x n, unshifted.  Feed it to
  * build_preconditioner(PICS_PRECOND_LEARNED). */
 int pics_net_correction(pics_net* net, pics_ctx* ctx, const float* features, float* correction);
+
+/* Autotuner.  Per group of equal-size slices, times the fused operator for
+ * each way of splitting a column tile's coil loop over 1, 2, 3, 4, 6, 8 or 12
+ * workgroups (the split adds the groups' partial sums in a second pass, in
+ * fixed order) and keeps the fastest for every later call.  Choices are
+ * cached per (GPU arch, CU count, m, n, largest coil count, slices) in
+ * $PICS_TUNE_CACHE (default ~/.cache/pics_autotune.txt).  Synchronises the
+ * stream; allocates the partial-sum workspace when a split is chosen.
+ * flags: PICS_TUNE_FORCE re-times even if cached; PICS_TUNE_NO_WRITE keeps
+ * the cache file unchanged. */
+#define PICS_TUNE_FORCE 1
+#define PICS_TUNE_NO_WRITE 2
+int pics_autotune(pics_ctx* ctx, int32_t flags);
+/* Chosen coil split per size group (in order of first appearance); returns
+ * the number of groups. */
+int pics_get_tuning(const pics_ctx* ctx, int32_t* coil_groups, int32_t max_groups);
 
 const char* pics_status_string(int status);
 const char* pics_last_error(const pics_ctx* ctx);

@@ -22,9 +22,12 @@ PICS_WARN_FALLBACK = 2
 MASK_LINES, MASK_2D = 0, 1
 WAVELET = {"none": 0, "haar": 1, "db4": 2}
 PRECOND = {"none": 0, "jacobi": 1, "circulant": 2, "learned": 3}
-TERM_DATA, TERM_TV, TERM_GAMMA, TERM_ALL = 1, 2, 4, 7
+TERM_DATA, TERM_TV, TERM_GAMMA, TERM_ALL, TERM_WAVELET_EXPLICIT = 1, 2, 4, 7, 8
 OPT_POLL_CHUNK = 1
 OPT_GRAPH_BUDGET = 2
+OPT_COIL_GROUPS = 3
+TUNE_FORCE = 1
+TUNE_NO_WRITE = 2
 
 
 class PicsError(RuntimeError):
@@ -41,25 +44,12 @@ class Desc(ctypes.Structure):
 
 _LIB = None
 
-EXPORTS = ["pics_create", "pics_destroy", "pics_sizes", "build_preconditioner", "apply_A", "apply_Minv",
-           "pics_fft2", "pics_wavelet", "pcg_solve", "split_bregman_recon", "pics_set_option",
-           "pics_status_string", "pics_last_error", "pics_features", "pics_probe_stats", "pics_net_create",
-           "pics_net_destroy", "pics_net_param_count", "pics_net_set_params", "pics_net_get_params",
-           "pics_net_get_grad", "pics_net_forward", "pics_net_loss_grad", "pics_net_adam_step",
-           "pics_net_correction"]
 
-
-def lib(path: str = LIB_PATH):
-    """Load libpics.so (raises if it is not built)."""
-    global _LIB
-    if _LIB is not None:
-        return _LIB
-    if not os.path.exists(path):
-        raise RuntimeError(f"{path} is not built: run `python -m paper_1710_01758_amd.build`")
-    L = ctypes.CDLL(path)
+def signatures():
+    """ctypes (restype, argtypes) of every function the C ABI exports."""
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     pi32, pdbl, pi64 = ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.POINTER(i64)
-    sig = {
+    return {
         "pics_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(Desc), vp, vp, vp]),
         "pics_destroy": (ctypes.c_int, [vp]),
         "pics_sizes": (ctypes.c_int, [vp, pi64, pi64, pi64]),
@@ -71,6 +61,8 @@ def lib(path: str = LIB_PATH):
         "pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, i32, pi32, pi32, pdbl, pi32]),
         "split_bregman_recon": (ctypes.c_int, [vp, vp, i32, i32, dbl, i32, pi32, vp, pi32]),
         "pics_set_option": (ctypes.c_int, [vp, i32, i64]),
+        "pics_autotune": (ctypes.c_int, [vp, i32]),
+        "pics_get_tuning": (ctypes.c_int, [vp, pi32, i32]),
         "pics_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pics_last_error": (ctypes.c_char_p, [vp]),
         "pics_features": (ctypes.c_int, [vp, vp, vp]),
@@ -86,6 +78,22 @@ def lib(path: str = LIB_PATH):
         "pics_net_adam_step": (ctypes.c_int, [vp, ctypes.c_float]),
         "pics_net_correction": (ctypes.c_int, [vp, vp, vp, vp]),
     }
+
+
+def library_path():
+    import pathlib
+    return pathlib.Path(LIB_PATH)
+
+
+def lib(path: str = LIB_PATH):
+    """Load libpics.so (raises if it is not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_1710_01758_amd.build`")
+    L = ctypes.CDLL(path)
+    sig = signatures()
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
@@ -154,6 +162,17 @@ class Context:
 
     def set_option(self, key: int, value: int):
         return self._check(self.L.pics_set_option(self.h, key, value))
+
+    def autotune(self, flags: int = 0):
+        """Time the coil splits of the fused operator per size group and keep
+        the fastest; returns the chosen split per group."""
+        self._check(self.L.pics_autotune(self.h, flags))
+        return self.tuning()
+
+    def tuning(self):
+        buf = (ctypes.c_int32 * 64)()
+        ng = self._check(self.L.pics_get_tuning(self.h, buf, 64))
+        return [int(buf[i]) for i in range(ng)]
 
     # -- entry points (same names as the C ABI)
     def build_preconditioner(self, kind: str = "circulant", correction=None, khat=None) -> int:

@@ -6,10 +6,11 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <sys/stat.h>
 #include <string>
 #include <vector>
 
-#include "../../include/pics.h"
+#include "pics.h"
 #include "fft.hpp"
 #include "internal.hpp"
 #include "learned.hpp"
@@ -31,6 +32,8 @@ struct pics_ctx {
     int m, n;
     std::vector<int> idx;
     int* idx_dev;
+    int coil_groups = 1;  // workgroups sharing one tile's coil loop (autotuned)
+    int nc_max = 0;
   };
   std::vector<Group> groups;
   int* all_idx_dev = nullptr;
@@ -71,11 +74,17 @@ struct pics_ctx {
     double tol;
     int budget, pk, n_inner;
     const int* hist;
+    int tuning;  // tuning generation: a new coil split or workspace needs a new graph
     bool operator==(const GraphKey& o) const {
-      return x == o.x && tol == o.tol && budget == o.budget && pk == o.pk && n_inner == o.n_inner && hist == o.hist;
+      return x == o.x && tol == o.tol && budget == o.budget && pk == o.pk && n_inner == o.n_inner && hist == o.hist &&
+             tuning == o.tuning;
     }
   } graph_key{};
   int graph_fallbacks = 0;       // solves that exceeded the budget (reconstruction redone host-polled)
+
+  float2* dpart = nullptr;       // per-coil-group partial data terms [groups][image-packed]
+  int dpart_groups = 0;
+  int tuning_gen = 0;            // bumped whenever a coil split or dpart changes
 };
 
 namespace {
@@ -220,6 +229,8 @@ const char* pics_status_string(int s) {
 
 const char* pics_last_error(const pics_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+namespace { int ensure_dpart(pics_ctx* c, int groups); }
+
 int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
   if (!c) return PICS_ERR_INVALID;
   if (key == PICS_OPT_POLL_CHUNK) {
@@ -230,6 +241,16 @@ int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
   if (key == PICS_OPT_GRAPH_BUDGET) {
     if (value < 0 || value > 64) return fail(c, PICS_ERR_INVALID, "graph budget out of range");
     c->graph_budget = (int)value;
+    return PICS_OK;
+  }
+  if (key == PICS_OPT_COIL_GROUPS) {
+    if (value < 1 || value > 64) return fail(c, PICS_ERR_INVALID, "coil split out of range");
+    int need = 1;
+    for (auto& g : c->groups) need = std::max(need, std::min((int)value, g.nc_max));
+    const int rc = ensure_dpart(c, need);
+    if (rc) return rc;
+    for (auto& g : c->groups) g.coil_groups = std::min((int)value, g.nc_max);
+    ++c->tuning_gen;
     return PICS_OK;
   }
   return fail(c, PICS_ERR_INVALID, "unknown option %d", key);
@@ -298,8 +319,10 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
     if (it == gidx.end()) {
       gidx[key] = (int)c->groups.size();
       c->groups.push_back({d.m, d.n, {s}, nullptr});
+      c->groups.back().nc_max = d.ncoils;
     } else {
       c->groups[it->second].idx.push_back(s);
+      c->groups[it->second].nc_max = std::max(c->groups[it->second].nc_max, (int)d.ncoils);
     }
   }
 
@@ -382,6 +405,7 @@ int pics_destroy(pics_ctx* c) {
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   if (c->hist) hipFree(c->hist);
+  if (c->dpart) hipFree(c->dpart);
   if (c->lock_block) hipFree(c->lock_block);
   if (c->st_host) hipHostFree(c->st_host);
   if (c->flag_host) hipHostFree(c->flag_host);
@@ -424,10 +448,23 @@ int build_preconditioner(pics_ctx* c, int32_t kind, const float* correction, flo
 int apply_A(pics_ctx* c, const void* x, void* y, int32_t terms) {
   if (!c) return PICS_ERR_INVALID;
   if (!x || !y || x == y) return fail(c, PICS_ERR_INVALID, "apply_A: null or aliased buffers");
-  if (terms < 0 || terms > PICS_TERM_ALL) return fail(c, PICS_ERR_INVALID, "apply_A: terms %d", terms);
+  if (terms < 0 || terms > (PICS_TERM_ALL | PICS_TERM_WAVELET_EXPLICIT))
+    return fail(c, PICS_ERR_INVALID, "apply_A: terms %d", terms);
+  const bool explicit_w = (terms & PICS_TERM_WAVELET_EXPLICIT) && (terms & PICS_TERM_GAMMA);
+  const int kterms = explicit_w ? (terms & (TERM_DATA | TERM_TV)) : (terms & TERM_ALL);
   for (auto& g : c->groups)
-    HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, terms, c->pk, 0.0, (const float2*)x,
-                               nullptr, nullptr, nullptr, (float2*)y, nullptr, nullptr));
+    HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, kterms, c->pk, 0.0, (const float2*)x,
+                               nullptr, nullptr, nullptr, (float2*)y, nullptr, nullptr, g.coil_groups, c->dpart,
+                               c->img_total));
+  if (explicit_w) {
+    // gam W^H W x through the wavelet kernels (coefficients in z, image in r)
+    TvArgs none{};
+    int rc = wavelet_analysis(c, (const float2*)x, 0, c->z, nullptr, nullptr, none);
+    if (rc) return rc;
+    rc = wavelet_synthesis(c, c->z, 0, c->r, nullptr, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    HIPCHK(c, launch_add_gamma(make_simple(c), make_ws(c), c->r, (const float2*)x, (float2*)y));
+  }
   return PICS_OK;
 }
 
@@ -490,7 +527,7 @@ int enq_pcg_setup(pics_ctx* c, const float2* b, float2* x, double tol, int maxit
   if (!q_valid)
     for (auto& g : c->groups)
       HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr,
-                                 nullptr, c->q, nullptr, nullptr));
+                                 nullptr, c->q, nullptr, nullptr, g.coil_groups, c->dpart, c->img_total));
   for (auto& g : c->groups)
     HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
                                 c->t));
@@ -515,7 +552,7 @@ int enq_pcg_iters(pics_ctx* c, float2* x, double tol, int k0, int count) {
     float2* pnew = pbuf[(k + 1) & 1];
     for (auto& g : c->groups)
       HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, pold,
-                                 pnew, c->q, nullptr, nullptr));
+                                 pnew, c->q, nullptr, nullptr, g.coil_groups, c->dpart, c->img_total));
     for (auto& g : c->groups)
       HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, pnew,
                                   nullptr, c->t));
@@ -616,7 +653,7 @@ int enq_shrinks(pics_ctx* c, const float2* x) {
 int enq_outer(pics_ctx* c, float2* x) {
   for (auto& g : c->groups)
     HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_OUTER, TERM_ALL, c->pk, 0.0, x, nullptr, nullptr,
-                               nullptr, c->q, c->g, c->g1));
+                               nullptr, c->q, c->g, c->g1, g.coil_groups, c->dpart, c->img_total));
   return PICS_OK;
 }
 
@@ -640,7 +677,7 @@ int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner
 }
 
 int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
-  const pics_ctx::GraphKey key{x, tol, budget, c->pk, n_inner, c->hist};
+  const pics_ctx::GraphKey key{x, tol, budget, c->pk, n_inner, c->hist, c->tuning_gen};
   if (c->graph_exec && c->graph_key == key) return PICS_OK;
   if (c->graph_exec) {
     HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
@@ -1046,6 +1083,148 @@ int pics_net_correction(pics_net* n, pics_ctx* c, const float* features, float* 
   }
   HIPCHK(c, hipStreamSynchronize(n->stream));
   return PICS_OK;
+}
+
+}  // extern "C"
+
+// ================================================================= autotuner
+// Per group of equal-size slices, time the fused operator for each coil split
+// (1, 2, 3, 4, 6, 8, 12 workgroups per column tile) with HIP events and keep
+// the fastest.  Results are cached per (GPU arch, CU count, m, n, largest coil
+// count, slices in the group) in a text file ($PICS_TUNE_CACHE, default
+// ~/.cache/pics_autotune.txt).
+namespace {
+
+std::string tune_cache_path() {
+  const char* p = getenv("PICS_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* h = getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/pics_autotune.txt";
+}
+
+std::string device_tag() {
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  char buf[128];
+  snprintf(buf, sizeof buf, "%s/%d", prop.gcnArchName, prop.multiProcessorCount);
+  for (char* q = buf; *q; ++q)
+    if (*q == ' ' || *q == ':') *q = '_';
+  return buf;
+}
+
+std::string group_key(const pics_ctx::Group& g) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s m%d n%d nc%d b%d", device_tag().c_str(), g.m, g.n, g.nc_max, (int)g.idx.size());
+  return buf;
+}
+
+std::map<std::string, int> read_tune_cache() {
+  std::map<std::string, int> out;
+  FILE* f = fopen(tune_cache_path().c_str(), "r");
+  if (!f) return out;
+  char line[256];
+  while (fgets(line, sizeof line, f)) {
+    std::string l(line);
+    const size_t eq = l.rfind('=');
+    if (eq == std::string::npos) continue;
+    out[l.substr(0, eq)] = atoi(l.c_str() + eq + 1);
+  }
+  fclose(f);
+  return out;
+}
+
+void write_tune_cache(const std::map<std::string, int>& m) {
+  const std::string path = tune_cache_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    std::string cmd;  // create the directory without a shell
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') {
+        std::string part = dir.substr(0, i);
+        mkdir(part.c_str(), 0755);
+      }
+  }
+  FILE* f = fopen(path.c_str(), "w");
+  if (!f) return;
+  for (auto& kv : m) fprintf(f, "%s=%d\n", kv.first.c_str(), kv.second);
+  fclose(f);
+}
+
+int ensure_dpart(pics_ctx* c, int groups) {
+  if (groups <= c->dpart_groups) return PICS_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->dpart) HIPCHK(c, hipFree(c->dpart));
+  c->dpart = nullptr;
+  HIPCHK(c, hipMalloc((void**)&c->dpart, sizeof(float2) * c->img_total * groups));
+  c->dpart_groups = groups;
+  ++c->tuning_gen;
+  return PICS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pics_autotune(pics_ctx* c, int32_t flags) {
+  if (!c) return PICS_ERR_INVALID;
+  std::map<std::string, int> cache = (flags & PICS_TUNE_FORCE) ? std::map<std::string, int>() : read_tune_cache();
+  bool changed = false;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  HIPCHK(c, launch_fill(c->stream, c->p, c->img_total, make_float2(1.f, 0.5f)));
+  for (auto& g : c->groups) {
+    const std::string key = group_key(g);
+    auto hit = cache.find(key);
+    if (hit != cache.end() && hit->second >= 1 && hit->second <= g.nc_max) {
+      int rc = ensure_dpart(c, hit->second);
+      if (rc) return rc;
+      g.coil_groups = hit->second;
+      continue;
+    }
+    const int cands[] = {1, 2, 3, 4, 6, 8, 12};
+    float best_ms = 1e30f;
+    int best = 1;
+    for (int G : cands) {
+      if (G > g.nc_max) break;
+      int rc = ensure_dpart(c, G);
+      if (rc) return rc;
+      auto run = [&]() {
+        return launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, c->pk, 0.0, c->p, nullptr,
+                                nullptr, nullptr, c->q, nullptr, nullptr, G, c->dpart, c->img_total);
+      };
+      for (int k = 0; k < 2; ++k) HIPCHK(c, run());
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      const int reps = 10;
+      for (int k = 0; k < reps; ++k) HIPCHK(c, run());
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+      if (ms < best_ms * 0.97f) {  // a split must win by 3% to be taken
+        best_ms = ms;
+        best = G;
+      }
+    }
+    g.coil_groups = best;
+    cache[key] = best;
+    changed = true;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ++c->tuning_gen;
+  if (changed && !(flags & PICS_TUNE_NO_WRITE)) write_tune_cache(cache);
+  return PICS_OK;
+}
+
+int pics_get_tuning(const pics_ctx* c, int32_t* coil_groups, int32_t max_groups) {
+  if (!c || !coil_groups) return PICS_ERR_INVALID;
+  for (int i = 0; i < (int)c->groups.size() && i < max_groups; ++i) coil_groups[i] = c->groups[i].coil_groups;
+  return (int)c->groups.size();
 }
 
 }  // extern "C"

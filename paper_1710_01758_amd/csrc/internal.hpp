@@ -61,6 +61,8 @@ enum { PK_NONE = 0, PK_JACOBI = 1, PK_CIRC = 2, PK_LEARNED = 3 };
 
 // column-tile apply modes
 enum { CA_APPLY = 0, CA_PCG = 1, CA_OUTER = 2 };
+// apply phases: one fused pass, or per-coil-group partial data terms + finish
+enum { AP_FUSED = 0, AP_PART = 1, AP_FIN = 2 };
 // apply term flags
 enum { TERM_DATA = 1, TERM_TV = 2, TERM_GAMMA = 4, TERM_ALL = 7 };
 // row-tile update modes
@@ -105,9 +107,13 @@ struct Simple {
 bool fft_size_supported(int N);
 
 // ---- FFT-path launchers (k_fft_ops.hip)
+// ngroups > 1 splits the coil loop over that many workgroups per tile
+// (partial data terms in dpart[group][image-packed], stride dstride elements)
+// and adds them in a second pass.
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            float2* g, const float2* g1);
+                            float2* g, const float2* g1, int ngroups = 1, float2* dpart = nullptr,
+                            long long dstride = 0);
 hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, const float2* b, const float2* q,
                              float2* x, float2* r, const float2* pn, float2* p, float2* t);
 hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t);
@@ -133,6 +139,7 @@ int wavelet_tiles(int m, int n, int level);
 hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, const float* corr, float* kraw,
                           float* kinv, float* jac, int* bad);
 hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v);
+hipError_t launch_add_gamma(const Simple& S, const Ws& w, const float2* wx, const float2* x, float2* y);
 hipError_t launch_pcg_record(hipStream_t st, const Ws& w, int nslices, int* hist_iters, int* hist_status,
                              int* counter);
 hipError_t launch_set_int(hipStream_t st, int* p, int v);

@@ -76,12 +76,18 @@ __device__ __forceinline__ void stage_twiddles(float2* s_tw, const float2* __res
 //      CA_PCG    p = zs + beta p_old (beta from the rho partials), written to pn;
 //                sigma = Re(p^H A p) partial
 //      CA_OUTER  p = xin; also g <- g + g1 - (data term)
+// PH AP_FUSED  everything in one launch
+//    AP_PART   grid.z = ngroups workgroups per column tile; group z takes coils
+//              z, z + ngroups, ... and writes its partial data term to
+//              dpart[z] (CA_PCG: group 0 also writes pn)
+//    AP_FIN    adds the partial sums in group order, then the diagonal terms
+//              and the mode's outputs (CA_PCG reads p back from pn)
 // ----------------------------------------------------------------------------
-template <int M, int MODE>
+template <int M, int MODE, int PH>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
     Ws w, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
     const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, float2* __restrict__ g,
-    const float2* __restrict__ g1) {
+    const float2* __restrict__ g1, int ngroups, float2* __restrict__ dpart, long long dstride) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT, TH = ColCfg<M>::THREADS;
   constexpr int TS = T + 2;  // tile stride with the two halo columns
   constexpr int HP = (2 * M + TH - 1) / TH;
@@ -94,7 +100,8 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int j0 = blockIdx.x * T;
   const int col = j0 + j;
-  const float2* __restrict__ xs = xin + sd.img;
+  // CA_PCG in the finishing pass: p was written to pn by the partial pass
+  const float2* __restrict__ xs = (MODE == CA_PCG ? (const float2*)pn : xin) + sd.img;
 
   int it = 0;
   float beta = 0.f;
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
     if (st->done) return;
     int status;
     if (pcg_should_stop(w, s, sd.m, tol, &status)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) pcg_mark_done(w, s, status, tol);
+      if (blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) pcg_mark_done(w, s, status, tol);
       return;
     }
     it = st->it_a;
@@ -128,50 +135,71 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
     hoff[k] = h < 2 * M ? i * n + (side ? jr : jl) : 0;
   }
   float2 pv[E], ph[HP];
-  if (MODE != CA_PCG) {
+  if (MODE != CA_PCG || PH == AP_FIN) {
 #pragma unroll
     for (int e = 0; e < E; ++e) pv[e] = xs[(t + NT * e) * n + col];
+    if (PH != AP_PART) {
 #pragma unroll
-    for (int k = 0; k < HP; ++k) ph[k] = xs[hoff[k]];
+      for (int k = 0; k < HP; ++k) ph[k] = xs[hoff[k]];
+    }
   } else {
     const float2* __restrict__ zs = zsrc + sd.img;
     const float2* __restrict__ po = pold + sd.img;
     const float* __restrict__ jc = w.jac + sd.img;
+    constexpr bool halo = PH == AP_FUSED;
 #pragma unroll
     for (int e = 0; e < E; ++e) pv[e] = zs[(t + NT * e) * n + col];
+    if (halo) {
 #pragma unroll
-    for (int k = 0; k < HP; ++k) ph[k] = zs[hoff[k]];
+      for (int k = 0; k < HP; ++k) ph[k] = zs[hoff[k]];
+    }
     if (pk == PK_JACOBI) {
       float jv[E], jh[HP];
 #pragma unroll
       for (int e = 0; e < E; ++e) jv[e] = jc[(t + NT * e) * n + col];
 #pragma unroll
-      for (int k = 0; k < HP; ++k) jh[k] = jc[hoff[k]];
-#pragma unroll
       for (int e = 0; e < E; ++e) pv[e] = cscale(pv[e], jv[e]);
+      if (halo) {
 #pragma unroll
-      for (int k = 0; k < HP; ++k) ph[k] = cscale(ph[k], jh[k]);
+        for (int k = 0; k < HP; ++k) jh[k] = jc[hoff[k]];
+#pragma unroll
+        for (int k = 0; k < HP; ++k) ph[k] = cscale(ph[k], jh[k]);
+      }
     }
     if (!first) {
       float2 ov[E], oh[HP];
 #pragma unroll
       for (int e = 0; e < E; ++e) ov[e] = po[(t + NT * e) * n + col];
 #pragma unroll
-      for (int k = 0; k < HP; ++k) oh[k] = po[hoff[k]];
-#pragma unroll
       for (int e = 0; e < E; ++e) pv[e] = make_float2(pv[e].x + beta * ov[e].x, pv[e].y + beta * ov[e].y);
+      if (halo) {
 #pragma unroll
-      for (int k = 0; k < HP; ++k) ph[k] = make_float2(ph[k].x + beta * oh[k].x, ph[k].y + beta * oh[k].y);
+        for (int k = 0; k < HP; ++k) oh[k] = po[hoff[k]];
+#pragma unroll
+        for (int k = 0; k < HP; ++k) ph[k] = make_float2(ph[k].x + beta * oh[k].x, ph[k].y + beta * oh[k].y);
+      }
     }
-    float2* __restrict__ pno = pn + sd.img;
+    if (PH == AP_FUSED || blockIdx.z == 0) {
+      float2* __restrict__ pno = pn + sd.img;
 #pragma unroll
-    for (int e = 0; e < E; ++e) pno[(t + NT * e) * n + col] = pv[e];
+      for (int e = 0; e < E; ++e) pno[(t + NT * e) * n + col] = pv[e];
+    }
   }
-  // data term sum_c conj(S_c) F^H R F (S_c p), coil maps of c + 1 in flight
+  // data term sum_c conj(S_c) F^H R F (S_c p), coil maps of c + 1 in flight.
+  // AP_PART: coils c = z, z + ngroups, ... of group z = blockIdx.z, result to
+  // dpart[z]; AP_FIN: the groups' partial sums added in group order.
   float2 acc[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
-  if ((terms & TERM_DATA) && sd.nc > 0) {
+  const int c0 = PH == AP_PART ? (int)blockIdx.z : 0;
+  const int cstep = PH == AP_PART ? ngroups : 1;
+  if (PH == AP_FIN) {
+    for (int gidx = 0; gidx < ngroups; ++gidx) {
+      const float2* __restrict__ dp = dpart + gidx * dstride + sd.img;
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], dp[(t + NT * e) * n + col]);
+    }
+  } else if ((terms & TERM_DATA) && c0 < sd.nc) {
     const uint8_t* mk = w.mask + sd.mask;
     unsigned mbits = 0u;  // bit e: frequency row t + NT e sampled
 #pragma unroll
@@ -181,10 +209,10 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
     const int plane = M * n;
     float2 sv[E], sn[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) sv[e] = S[NT * e * n];
-    for (int c = 0; c < sd.nc; ++c) {
-      if (c + 1 < sd.nc) {
-        const float2* __restrict__ Sn = S + (long long)(c + 1) * plane;
+    for (int e = 0; e < E; ++e) sv[e] = S[(long long)c0 * plane + NT * e * n];
+    for (int c = c0; c < sd.nc; c += cstep) {
+      if (c + cstep < sd.nc) {
+        const float2* __restrict__ Sn = S + (long long)(c + cstep) * plane;
 #pragma unroll
         for (int e = 0; e < E; ++e) sn[e] = Sn[NT * e * n];
       }
@@ -200,6 +228,12 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
 #pragma unroll
       for (int e = 0; e < E; ++e) sv[e] = sn[e];
     }
+  }
+  if (PH == AP_PART) {
+    float2* __restrict__ dp = dpart + (long long)blockIdx.z * dstride + sd.img;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dp[(t + NT * e) * n + col] = acc[e];
+    return;
   }
   __syncthreads();  // the FFTs are done with the LDS buffer
 
@@ -621,22 +655,42 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, co
 
 #define PICS_FFT_SIZES(X) X(64) X(128) X(192) X(224) X(256) X(320) X(512)
 
+template <int M, int PH>
+void launch_col_apply_phase(dim3 grid, const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
+                            const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
+                            float2* g, const float2* g1, int ngroups, float2* dpart, long long dstride) {
+  const dim3 block(ColCfg<M>::THREADS);
+  if (mode == CA_PCG)
+    hipLaunchKernelGGL((k_col_apply<M, CA_PCG, PH>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc, pold,
+                       pn, out, g, g1, ngroups, dpart, dstride);
+  else if (mode == CA_OUTER && PH != AP_PART)  // the partial pass of CA_OUTER is CA_APPLY's
+    hipLaunchKernelGGL((k_col_apply<M, PH == AP_PART ? CA_APPLY : CA_OUTER, PH>), grid, block, 0, L.stream, w, terms,
+                       pk, tol, xin, zsrc, pold, pn, out, g, g1, ngroups, dpart, dstride);
+  else
+    hipLaunchKernelGGL((k_col_apply<M, CA_APPLY, PH>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc, pold,
+                       pn, out, g, g1, ngroups, dpart, dstride);
+}
+
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            float2* g, const float2* g1) {
+                            float2* g, const float2* g1, int ngroups, float2* dpart, long long dstride) {
+  const int split = (ngroups > 1 && (terms & TERM_DATA)) ? ngroups : 1;
+  if (split > 1 && !dpart) return hipErrorInvalidValue;
   const dim3 grid(L.n / kColT, L.count);
   switch (L.m) {
-#define PICS_CASE(M)                                                                                         \
-  case M:                                                                                                    \
-    if (mode == CA_PCG)                                                                                      \
-      hipLaunchKernelGGL((k_col_apply<M, CA_PCG>), grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, terms, pk, \
-                         tol, xin, zsrc, pold, pn, out, g, g1);                                              \
-    else if (mode == CA_OUTER)                                                                               \
-      hipLaunchKernelGGL((k_col_apply<M, CA_OUTER>), grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, terms,   \
-                         pk, tol, xin, zsrc, pold, pn, out, g, g1);                                          \
-    else                                                                                                     \
-      hipLaunchKernelGGL((k_col_apply<M, CA_APPLY>), grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, terms,   \
-                         pk, tol, xin, zsrc, pold, pn, out, g, g1);                                          \
+#define PICS_CASE(M)                                                                                              \
+  case M:                                                                                                         \
+    if (split == 1) {                                                                                             \
+      launch_col_apply_phase<M, AP_FUSED>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, g, g1, 1,   \
+                                          dpart, dstride);                                                       \
+    } else {                                                                                                      \
+      launch_col_apply_phase<M, AP_PART>(dim3(grid.x, grid.y, split), L, w, mode, terms, pk, tol, xin, zsrc,      \
+                                         pold, pn, out, g, g1, split, dpart, dstride);                           \
+      const hipError_t e = hipGetLastError();                                                                     \
+      if (e != hipSuccess) return e;                                                                              \
+      launch_col_apply_phase<M, AP_FIN>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, g, g1, split, \
+                                        dpart, dstride);                                                         \
+    }                                                                                                             \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE

@@ -437,6 +437,19 @@ __global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict_
   if (badl) atomicOr(bad, 1);
 }
 
+// y += gam W^H W x, given wx = W^H W x (x itself for slices without a wavelet)
+__global__ __launch_bounds__(256) void k_add_gamma(Ws w, const float2* __restrict__ wx, const float2* __restrict__ x,
+                                                   float2* __restrict__ y) {
+  const int s = blockIdx.y;
+  const SliceDev sd = w.sl[s];
+  const long long np = (long long)sd.m * sd.n;
+  const float2* src = (sd.levels > 0 && sd.wavelet != 0) ? wx : x;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += (long long)gridDim.x * blockDim.x) {
+    const float2 a = src[sd.img + p], b = y[sd.img + p];
+    y[sd.img + p] = make_float2(b.x + sd.gam * a.x, b.y + sd.gam * a.y);
+  }
+}
+
 __global__ void k_fill(float2* p, long long count, float2 v) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
@@ -504,6 +517,11 @@ hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, cons
   dim3 grid = simple_grid(S);
   if (grid.x > 64) grid.x = 64;
   hipLaunchKernelGGL(k_build_k, grid, dim3(256), 0, S.stream, w, pbar, corr, kraw, kinv, jac, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_gamma(const Simple& S, const Ws& w, const float2* wx, const float2* x, float2* y) {
+  hipLaunchKernelGGL(k_add_gamma, simple_grid(S), dim3(256), 0, S.stream, w, wx, x, y);
   return hipGetLastError();
 }
 

@@ -1,0 +1,105 @@
+"""The C ABI without a GPU: the built library loads, exports every function
+that include/pics.h declares, the Python binding declares a signature for each
+of them, the binding's constants equal the header's, and the host-only entry
+points (status strings, argument checks before any device work) behave."""
+import ctypes
+import pathlib
+import re
+
+import pytest
+
+from paper_1710_01758_amd import binding as B
+
+ROOT = pathlib.Path(__file__).resolve().parent.parent
+HEADER = ROOT / "include" / "pics.h"
+
+
+def _declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\*?([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def _defines():
+    out = {}
+    for name, val in re.findall(r"^#define\s+(PICS_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", HEADER.read_text(), flags=re.M):
+        out[name] = int(val)
+    return out
+
+
+@pytest.fixture(scope="module")
+def lib():
+    path = B.library_path()
+    if not path.exists():
+        pytest.skip("libpics.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(str(path))
+
+
+def test_header_parses():
+    names = _declared_functions()
+    for must in ("pics_create", "build_preconditioner", "apply_A", "apply_Minv", "pcg_solve",
+                 "split_bregman_recon", "pics_autotune", "pics_net_loss_grad"):
+        assert must in names, must
+
+
+def test_library_exports_every_declared_function(lib):
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_function():
+    sig = B.signatures()
+    missing = [n for n in _declared_functions() if n not in sig]
+    assert not missing, missing
+
+
+def test_binding_constants_match_header():
+    d = _defines()
+    assert d["PICS_OK"] == B.PICS_OK
+    assert d["PICS_WARN_MAXIT"] == B.PICS_WARN_MAXIT
+    assert d["PICS_WARN_FALLBACK"] == B.PICS_WARN_FALLBACK
+    assert (d["PICS_MASK_LINES"], d["PICS_MASK_2D"]) == (B.MASK_LINES, B.MASK_2D)
+    assert d["PICS_WAVELET_NONE"] == B.WAVELET["none"]
+    assert d["PICS_WAVELET_HAAR"] == B.WAVELET["haar"]
+    assert d["PICS_WAVELET_DB4"] == B.WAVELET["db4"]
+    for k in ("none", "jacobi", "circulant", "learned"):
+        assert d["PICS_PRECOND_" + k.upper()] == B.PRECOND[k]
+    assert d["PICS_TERM_DATA"] == B.TERM_DATA
+    assert d["PICS_TERM_TV"] == B.TERM_TV
+    assert d["PICS_TERM_GAMMA"] == B.TERM_GAMMA
+    assert d["PICS_TERM_ALL"] == B.TERM_ALL
+    assert d["PICS_TERM_WAVELET_EXPLICIT"] == B.TERM_WAVELET_EXPLICIT
+    assert d["PICS_OPT_POLL_CHUNK"] == B.OPT_POLL_CHUNK
+    assert d["PICS_OPT_GRAPH_BUDGET"] == B.OPT_GRAPH_BUDGET
+    assert d["PICS_OPT_COIL_GROUPS"] == B.OPT_COIL_GROUPS
+    assert d["PICS_TUNE_FORCE"] == B.TUNE_FORCE
+    assert d["PICS_TUNE_NO_WRITE"] == B.TUNE_NO_WRITE
+
+
+def test_desc_layout_matches_header():
+    # pics_desc: m, n, ncoils, mask_kind, wavelet, levels (int32) then mu, lambda, gamma (double)
+    assert ctypes.sizeof(B.Desc) == 6 * 4 + 3 * 8
+    assert B.Desc.mu.offset == 24
+
+
+def test_status_strings_and_null_checks(lib):
+    lib.pics_status_string.restype = ctypes.c_char_p
+    lib.pics_status_string.argtypes = [ctypes.c_int]
+    d = _defines()
+    seen = set()
+    for name, code in d.items():
+        if name.startswith("PICS_ERR_") or name.startswith("PICS_WARN_") or name == "PICS_OK":
+            s = lib.pics_status_string(code).decode()
+            assert s and s not in seen, (name, s)
+            seen.add(s)
+    # null handles are rejected before any device work
+    for fn, nargs in (("pics_destroy", 1), ("apply_A", 4), ("apply_Minv", 3), ("pics_autotune", 2)):
+        f = getattr(lib, fn)
+        f.restype = ctypes.c_int
+        args = [None] + [0] * (nargs - 1)
+        assert f(*args) == d["PICS_ERR_INVALID"] or fn == "pics_destroy"
+    lib.pics_net_param_count.restype = ctypes.c_int64
+    from oracle import learned as OL
+    assert lib.pics_net_param_count() == OL.param_count()

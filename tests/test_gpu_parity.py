@@ -73,7 +73,7 @@ def _check_apply(torch, B, insts, tol=1e-5):
     xs = [gen.random_image(100 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
     xd = B.to_device(B.pack_images(xs))
     yd = torch.empty_like(xd)
-    for terms in (B.TERM_ALL, B.TERM_DATA, B.TERM_TV | B.TERM_GAMMA):
+    for terms in (B.TERM_ALL, B.TERM_DATA, B.TERM_TV | B.TERM_GAMMA, B.TERM_ALL | B.TERM_WAVELET_EXPLICIT):
         ctx.apply_A(xd, yd, terms)
         got = B.unpack_images(_host(yd), [(it.spec.m, it.spec.n) for it in insts])
         for it, x, g in zip(insts, xs, got):
@@ -82,7 +82,8 @@ def _check_apply(torch, B, insts, tol=1e-5):
             mu = s.mu if terms & B.TERM_DATA else 0.0
             lam = s.lam if terms & B.TERM_TV else 0.0
             gam = s.gam if terms & B.TERM_GAMMA else 0.0
-            ref = ops.apply_A(x, it.sens, r2d, mu, lam, gam)
+            wave = owav.make(s.wavelet, s.levels) if terms & B.TERM_WAVELET_EXPLICIT else None
+            ref = ops.apply_A(x, it.sens, r2d, mu, lam, gam, wave)
             assert H.rel_err(g, ref) < tol, (s.m, s.n, terms, H.rel_err(g, ref))
 
 
@@ -327,3 +328,102 @@ def test_split_bregman_graph_equals_host_polled(torch, B, scale):
     _, _, x_small, it_small = _sb_run(torch, B, insts, budget=1)
     assert np.array_equal(it_small, it_ref)
     assert np.array_equal(_host(x_small), ref)
+
+
+# ---------------------------------------------------------------- coil split
+
+@pytest.mark.parametrize("groups", [2, 5, 12])
+def test_apply_A_coil_split_matches_oracle(torch, B, groups):
+    """Splitting each column tile's coil loop over several workgroups (5 does
+    not divide 12 coils) keeps apply_A within tolerance of the oracle."""
+    _say(f"apply_A coil split {groups}")
+    insts = [_inst(gen.CFG2, gen.eval_seed(2))]
+    specs = gen.cfg4_specs(nslices=4)
+    insts += [_inst(sp, 1200 + i) for i, sp in enumerate(specs)]
+    ctx, _ = _ctx(B, insts)
+    ctx.set_option(B.OPT_COIL_GROUPS, groups)
+    xs = [gen.random_image(300 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
+    xd = B.to_device(B.pack_images(xs))
+    yd = torch.empty_like(xd)
+    for terms in (B.TERM_ALL, B.TERM_DATA):
+        ctx.apply_A(xd, yd, terms)
+        got = B.unpack_images(_host(yd), [(it.spec.m, it.spec.n) for it in insts])
+        for it, x, g in zip(insts, xs, got):
+            s = it.spec
+            lam, gam = (s.lam, s.gam) if terms == B.TERM_ALL else (0.0, 0.0)
+            ref = ops.apply_A(x, it.sens, it.mask2d.astype(np.float64), s.mu, lam, gam)
+            assert H.rel_err(g, ref) < 1e-5, (groups, s.m, s.n, s.ncoils, H.rel_err(g, ref))
+    # a second call gives the same bits (fixed-order partial sums)
+    y2 = torch.empty_like(xd)
+    ctx.apply_A(xd, y2, B.TERM_DATA)
+    assert torch.equal(yd, y2)
+
+
+def test_pcg_coil_split_locked_and_deterministic(torch, B):
+    _say("pcg coil split 3")
+    it = _inst(gen.CFG2, gen.eval_seed(2))
+    s = it.spec
+    r2d = it.mask2d.astype(np.float64)
+    A = lambda v: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
+    b = _rhs(it)
+    ref = opcg.pcg(A, b, np.zeros_like(b), osb.make_minv("circulant", it.sens, r2d, s.mu, s.lam, s.gam), 1e-3, 1000)
+    ctx, _ = _ctx(B, [it])
+    ctx.build_preconditioner("circulant")
+    ctx.set_option(B.OPT_COIL_GROUPS, 3)
+    bd = B.to_device(b.astype(np.complex64).ravel())
+    outs = []
+    for _ in range(2):
+        xd = torch.zeros_like(bd)
+        iters, _, _, _ = ctx.pcg_solve(bd, xd, 0.0, 0, maxit_per_slice=[ref.iters])
+        assert iters[0] == ref.iters
+        outs.append(_host(xd))
+    assert H.rel_err(outs[0].reshape(s.m, s.n), ref.x) < 1e-4
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_split_bregman_coil_split_graph(torch, B):
+    """Split Bregman with a coil split: graph-replayed equals host-polled bit
+    for bit, and the unsplit run locked to the same PCG counts agrees."""
+    _say("sb coil split graph")
+    insts = [_inst(gen.CFG2, gen.eval_seed(2 + 100 * i)) for i in range(2)]
+
+    def run(groups, budget, lock=None):
+        ctx, ksp = _ctx(B, insts)
+        ctx.build_preconditioner("circulant")
+        ctx.set_option(B.OPT_COIL_GROUPS, groups)
+        ctx.set_option(B.OPT_GRAPH_BUDGET, budget)
+        x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+        it, _ = ctx.split_bregman_recon(ksp, x, n_outer=4, tol=1e-3, maxit=100, lock=lock)
+        ctx.close()
+        return _host(x), it
+
+    xp, itp = run(4, 0)
+    xg, itg = run(4, 8)
+    assert np.array_equal(itp, itg)
+    assert np.array_equal(xp, xg)
+    x1, _ = run(1, 0, lock=itp)
+    assert H.rel_err(xp, x1) < 1e-3, H.rel_err(xp, x1)
+
+
+def test_autotune_picks_a_valid_split(torch, B, tmp_path, monkeypatch):
+    _say("autotune")
+    monkeypatch.setenv("PICS_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    specs = gen.cfg4_specs(nslices=6)
+    insts = [_inst(sp, 1300 + i) for i, sp in enumerate(specs)]
+    ctx, _ = _ctx(B, insts)
+    choice = ctx.autotune()
+    assert len(choice) >= 1 and all(c in (1, 2, 3, 4, 6, 8, 12) for c in choice), choice
+    assert (tmp_path / "tune.txt").exists()
+    # a second context reads the cache and takes the same choice
+    ctx2, _ = _ctx(B, insts)
+    assert ctx2.autotune() == choice
+    # results after tuning still match the oracle
+    xs = [gen.random_image(400 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
+    xd = B.to_device(B.pack_images(xs))
+    yd = torch.empty_like(xd)
+    ctx2.apply_A(xd, yd, B.TERM_ALL)
+    got = B.unpack_images(_host(yd), [(it.spec.m, it.spec.n) for it in insts])
+    for it, x, g in zip(insts, xs, got):
+        s = it.spec
+        ref = ops.apply_A(x, it.sens, it.mask2d.astype(np.float64), s.mu, s.lam, s.gam)
+        assert H.rel_err(g, ref) < 1e-5
