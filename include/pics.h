@@ -168,10 +168,16 @@ int split_bregman_recon(pics_ctx* ctx, const void* kspace, int32_t n_outer, int3
  *   0 disables the graph.  Default 2.
  * PICS_OPT_COIL_GROUPS: split every column tile's coil loop over this many
  *   workgroups (clamped to each group's coil count), overriding the
- *   autotuner; 1 = no split (the default before pics_autotune). */
+ *   autotuner; 1 = no split (the default before pics_autotune).
+ * PICS_OPT_CONCURRENT_GROUPS: 1 (default) runs the per-size-group kernels of
+ *   a batch with several slice sizes on side streams of the context (forked
+ *   from and joined back to the caller's stream with events, also under
+ *   graph capture); 0 runs them one group after the other on the caller's
+ *   stream.  Results are identical either way. */
 #define PICS_OPT_POLL_CHUNK 1
 #define PICS_OPT_GRAPH_BUDGET 2
 #define PICS_OPT_COIL_GROUPS 3
+#define PICS_OPT_CONCURRENT_GROUPS 4
 int pics_set_option(pics_ctx* ctx, int32_t key, int64_t value);
 
 /* ---------------------------------------------------------------------------

@@ -26,6 +26,7 @@ TERM_DATA, TERM_TV, TERM_GAMMA, TERM_ALL, TERM_WAVELET_EXPLICIT = 1, 2, 4, 7, 8
 OPT_POLL_CHUNK = 1
 OPT_GRAPH_BUDGET = 2
 OPT_COIL_GROUPS = 3
+OPT_CONCURRENT_GROUPS = 4
 TUNE_FORCE = 1
 TUNE_NO_WRITE = 2
 

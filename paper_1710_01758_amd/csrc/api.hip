@@ -34,6 +34,7 @@ struct pics_ctx {
     int* idx_dev;
     int coil_groups = 1;  // workgroups sharing one tile's coil loop (autotuned)
     int nc_max = 0;
+    int sidx = 0;         // index of the group's side stream
   };
   std::vector<Group> groups;
   int* all_idx_dev = nullptr;
@@ -82,6 +83,14 @@ struct pics_ctx {
   } graph_key{};
   int graph_fallbacks = 0;       // solves that exceeded the budget (reconstruction redone host-polled)
 
+  // Size groups touch disjoint slices, so their per-group kernels run on side
+  // streams, forked from and joined back to the context's stream with events.
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_done;
+  hipEvent_t fork_ev = nullptr;
+  int forked = 0;
+  bool concurrent_groups = true;
+
   float2* dpart = nullptr;       // per-coil-group partial data terms [groups][image-packed]
   int dpart_groups = 0;
   int tuning_gen = 0;            // bumped whenever a coil split or dpart changes
@@ -121,7 +130,7 @@ Ws make_ws(const pics_ctx* c) {
 
 Launch make_launch(const pics_ctx* c, const pics_ctx::Group& g) {
   Launch L;
-  L.stream = c->stream;
+  L.stream = c->forked ? c->side[g.sidx] : c->stream;
   L.m = g.m;
   L.n = g.n;
   L.count = (int)g.idx.size();
@@ -136,6 +145,36 @@ Simple make_simple(const pics_ctx* c) {
   S.max_pixels = c->max_pixels;
   return S;
 }
+
+// Scope in which make_launch hands each size group its side stream: the
+// side streams wait for the work already on the context's stream, and the
+// context's stream waits for all of them when the scope ends.  Works under
+// stream capture (the side streams join the capture through the events).
+struct GroupFork {
+  pics_ctx* c;
+  bool on = false;
+  hipError_t err = hipSuccess;
+  explicit GroupFork(pics_ctx* cc) : c(cc) {
+    if (c->side.empty() || !c->concurrent_groups || c->forked) return;
+    err = hipEventRecord(c->fork_ev, c->stream);
+    for (size_t i = 0; i < c->side.size() && err == hipSuccess; ++i) err = hipStreamWaitEvent(c->side[i], c->fork_ev, 0);
+    on = err == hipSuccess;
+    c->forked = on;
+  }
+  hipError_t join() {
+    if (!on) return err;
+    on = false;
+    c->forked = 0;
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < c->side.size(); ++i) {
+      hipError_t e1 = hipEventRecord(c->side_done[i], c->side[i]);
+      if (e1 == hipSuccess) e1 = hipStreamWaitEvent(c->stream, c->side_done[i], 0);
+      if (e == hipSuccess) e = e1;
+    }
+    return e;
+  }
+  ~GroupFork() { join(); }
+};
 
 // Ws whose group table is the group's slice list (grid.y -> slice)
 Ws ws_for(const pics_ctx* c, const pics_ctx::Group& g) {
@@ -241,6 +280,12 @@ int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
   if (key == PICS_OPT_GRAPH_BUDGET) {
     if (value < 0 || value > 64) return fail(c, PICS_ERR_INVALID, "graph budget out of range");
     c->graph_budget = (int)value;
+    return PICS_OK;
+  }
+  if (key == PICS_OPT_CONCURRENT_GROUPS) {
+    if (value < 0 || value > 1) return fail(c, PICS_ERR_INVALID, "concurrent groups: 0 or 1");
+    c->concurrent_groups = value != 0;
+    ++c->tuning_gen;
     return PICS_OK;
   }
   if (key == PICS_OPT_COIL_GROUPS) {
@@ -388,7 +433,22 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   for (auto& g : c->groups)
     ok = ok && hipMemcpy(g.idx_dev, g.idx.data(), sizeof(int) * g.idx.size(), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemset(c->part, 0, sizeof(double) * nslices * kSlots * kPartMax) == hipSuccess;
+  if (ok && c->groups.size() > 1) {
+    ok = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (size_t i = 0; i < c->groups.size() && ok; ++i) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      if (st) c->side.push_back(st);
+      if (ev) c->side_done.push_back(ev);
+      c->groups[i].sidx = (int)i;
+    }
+  }
   if (!ok) {
+    for (auto st : c->side) hipStreamDestroy(st);
+    for (auto ev : c->side_done) hipEventDestroy(ev);
+    if (c->fork_ev) hipEventDestroy(c->fork_ev);
     hipHostFree(c->st_host);
     hipHostFree(c->flag_host);
     hipFree(c->block);
@@ -406,6 +466,9 @@ int pics_destroy(pics_ctx* c) {
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   if (c->hist) hipFree(c->hist);
   if (c->dpart) hipFree(c->dpart);
+  for (auto st : c->side) hipStreamDestroy(st);
+  for (auto ev : c->side_done) hipEventDestroy(ev);
+  if (c->fork_ev) hipEventDestroy(c->fork_ev);
   if (c->lock_block) hipFree(c->lock_block);
   if (c->st_host) hipHostFree(c->st_host);
   if (c->flag_host) hipHostFree(c->flag_host);
@@ -426,7 +489,11 @@ int build_preconditioner(pics_ctx* c, int32_t kind, const float* correction, flo
   int rc = PICS_OK;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const float* corr = (kind == PICS_PRECOND_LEARNED && attempt == 0) ? correction : nullptr;
-    for (auto& g : c->groups) HIPCHK(c, launch_col_coil_power(make_launch(c, g), ws_for(c, g), c->pbar, c->jac));
+    {
+      GroupFork fk(c);
+      for (auto& g : c->groups) HIPCHK(c, launch_col_coil_power(make_launch(c, g), ws_for(c, g), c->pbar, c->jac));
+      HIPCHK(c, fk.join());
+    }
     HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
     HIPCHK(c, launch_build_k(make_simple(c), w, c->pbar, corr, c->kraw, c->kinv, c->jac, c->bad));
     HIPCHK(c, hipMemcpyAsync(c->flag_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -452,10 +519,14 @@ int apply_A(pics_ctx* c, const void* x, void* y, int32_t terms) {
     return fail(c, PICS_ERR_INVALID, "apply_A: terms %d", terms);
   const bool explicit_w = (terms & PICS_TERM_WAVELET_EXPLICIT) && (terms & PICS_TERM_GAMMA);
   const int kterms = explicit_w ? (terms & (TERM_DATA | TERM_TV)) : (terms & TERM_ALL);
-  for (auto& g : c->groups)
-    HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, kterms, c->pk, 0.0, (const float2*)x,
-                               nullptr, nullptr, nullptr, (float2*)y, nullptr, nullptr, g.coil_groups, c->dpart,
-                               c->img_total));
+  {
+    GroupFork fk(c);
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, kterms, c->pk, 0.0, (const float2*)x,
+                                 nullptr, nullptr, nullptr, (float2*)y, g.coil_groups, c->dpart,
+                                 c->img_total));
+    HIPCHK(c, fk.join());
+  }
   if (explicit_w) {
     // gam W^H W x through the wavelet kernels (coefficients in z, image in r)
     TvArgs none{};
@@ -472,9 +543,13 @@ int apply_Minv(pics_ctx* c, const void* r, void* z) {
   if (!c) return PICS_ERR_INVALID;
   if (!r || !z || r == z) return fail(c, PICS_ERR_INVALID, "apply_Minv: null or aliased buffers");
   if (c->pk != PK_CIRC && c->pk != PK_LEARNED) return fail(c, PICS_ERR_STATE, "apply_Minv: no circulant build");
-  for (auto& g : c->groups) HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 0, (const float2*)r, c->t));
-  for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 0, 0, 0.0, c->t));
-  for (auto& g : c->groups) HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 0, c->t, (float2*)z));
+  GroupFork fk(c);
+  for (auto& g : c->groups) {
+    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 0, (const float2*)r, c->t));
+    HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 0, 0, 0.0, c->t));
+    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 0, c->t, (float2*)z));
+  }
+  HIPCHK(c, fk.join());
   return PICS_OK;
 }
 
@@ -482,9 +557,12 @@ int pics_fft2(pics_ctx* c, const void* in, void* out, int32_t inverse) {
   if (!c) return PICS_ERR_INVALID;
   if (!in || !out) return fail(c, PICS_ERR_INVALID, "fft2: null buffer");
   const int inv = inverse ? 1 : 0;
-  for (auto& g : c->groups)
+  GroupFork fk(c);
+  for (auto& g : c->groups) {
     HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), inv, 0, (const float2*)in, c->t));
-  for (auto& g : c->groups) HIPCHK(c, launch_col_fft(make_launch(c, g), ws_for(c, g), inv, c->t, (float2*)out));
+    HIPCHK(c, launch_col_fft(make_launch(c, g), ws_for(c, g), inv, c->t, (float2*)out));
+  }
+  HIPCHK(c, fk.join());
   return PICS_OK;
 }
 
@@ -524,17 +602,25 @@ int enq_pcg_setup(pics_ctx* c, const float2* b, float2* x, double tol, int maxit
   const int pk = c->pk;
   const bool circ = pk == PK_CIRC || pk == PK_LEARNED;
   HIPCHK(c, launch_pcg_reset(c->stream, w, c->nslices, maxit, maxit_dev));
-  if (!q_valid)
-    for (auto& g : c->groups)
-      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr,
-                                 nullptr, c->q, nullptr, nullptr, g.coil_groups, c->dpart, c->img_total));
-  for (auto& g : c->groups)
-    HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
-                                c->t));
+  {
+    GroupFork fk(c);
+    for (auto& g : c->groups) {
+      if (!q_valid)
+        HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr,
+                                   nullptr, c->q, g.coil_groups, c->dpart, c->img_total));
+      HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
+                                  c->t));
+    }
+    HIPCHK(c, fk.join());
+  }
   HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 1, x));
   if (circ) {
-    for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
-    for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
+    GroupFork fk(c);
+    for (auto& g : c->groups) {
+      HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
+      HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
+    }
+    HIPCHK(c, fk.join());
   }
   return PICS_OK;
 }
@@ -547,20 +633,22 @@ int enq_pcg_iters(pics_ctx* c, float2* x, double tol, int k0, int count) {
   const bool circ = pk == PK_CIRC || pk == PK_LEARNED;
   const float2* zsrc = circ ? c->z : c->r;
   float2* pbuf[2] = {c->p, c->pn};
-  for (int k = k0; k < k0 + count; ++k) {
-    float2* pold = pbuf[k & 1];
-    float2* pnew = pbuf[(k + 1) & 1];
-    for (auto& g : c->groups)
+  GroupFork fk(c);
+  for (auto& g : c->groups) {
+    for (int k = k0; k < k0 + count; ++k) {
+      float2* pold = pbuf[k & 1];
+      float2* pnew = pbuf[(k + 1) & 1];
       HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, pold,
-                                 pnew, c->q, nullptr, nullptr, g.coil_groups, c->dpart, c->img_total));
-    for (auto& g : c->groups)
+                                 pnew, c->q, g.coil_groups, c->dpart, c->img_total));
       HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, pnew,
                                   nullptr, c->t));
-    if (circ) {
-      for (auto& g : c->groups) HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
-      for (auto& g : c->groups) HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
+      if (circ) {
+        HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
+        HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
+      }
     }
   }
+  HIPCHK(c, fk.join());
   return PICS_OK;
 }
 
@@ -636,24 +724,19 @@ int enq_rhs(pics_ctx* c) {
   return PICS_OK;
 }
 
-// Split Bregman steps 6-11: TV and wavelet shrinks and Bregman updates
-int enq_shrinks(pics_ctx* c, const float2* x) {
+// Split Bregman steps 6-11: TV and wavelet shrinks and Bregman updates on the
+// solve's x, with the outer update fused in: q = A x = b - r for the next
+// solve's set-up, and, after the last inner solve of an outer iteration
+// (outer_step), steps 13-15 in the image domain, g <- g + g_1 - A_data x.
+int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step) {
   const Ws w = make_ws(c);
   const Simple S = make_simple(c);
-  if (c->any_nowavelet) HIPCHK(c, launch_tv_shrink(S, w, 1, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+  const OuterArgs oa{outer_step ? 2 : 1, c->rhs, c->r, c->q, c->g, c->g1};
+  if (c->any_nowavelet) HIPCHK(c, launch_tv_shrink(S, w, 1, oa, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
   if (c->any_wavelet) {
-    TvArgs tv{1, c->bx, c->by, c->ux, c->uy};
+    TvArgs tv{1, c->bx, c->by, c->ux, c->uy, oa};
     return wavelet_analysis(c, x, 1, nullptr, c->bw, c->uw, tv);
   }
-  return PICS_OK;
-}
-
-// Split Bregman steps 13-15 in the image domain: g_{j+1} = g_j + g_1 - A_data x;
-// the same kernel leaves A x in q for the next solve's set-up.
-int enq_outer(pics_ctx* c, float2* x) {
-  for (auto& g : c->groups)
-    HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_OUTER, TERM_ALL, c->pk, 0.0, x, nullptr, nullptr,
-                               nullptr, c->q, c->g, c->g1, g.coil_groups, c->dpart, c->img_total));
   return PICS_OK;
 }
 
@@ -664,16 +747,16 @@ int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner
   for (int ji = 0; ji < n_inner; ++ji) {
     int rc = enq_rhs(c);
     if (rc) return rc;
-    rc = enq_pcg_setup(c, c->rhs, x, tol, budget, nullptr, ji == 0);
+    rc = enq_pcg_setup(c, c->rhs, x, tol, budget, nullptr, true);
     if (rc) return rc;
     rc = enq_pcg_iters(c, x, tol, 0, budget);
     if (rc) return rc;
     HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 0, x));
     HIPCHK(c, launch_pcg_record(c->stream, w, c->nslices, c->hist, c->hist + c->hist_cap / 2, c->solve_counter));
-    rc = enq_shrinks(c, x);
+    rc = enq_shrinks(c, x, ji == n_inner - 1);
     if (rc) return rc;
   }
-  return enq_outer(c, x);
+  return PICS_OK;
 }
 
 int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
@@ -762,10 +845,14 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
   for (int attempt = 0; attempt < 2; ++attempt) {
     const bool graph_now = use_graph && attempt == 0;
     // Algorithm 1, step 1: coil images F^H R y_i, root sum of squares, g_1
-    for (auto& g : c->groups)
-      HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, (const float2*)kspace, c->coiltmp));
-    for (auto& g : c->groups)
-      HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, x));
+    {
+      GroupFork fk(c);
+      for (auto& g : c->groups) {
+        HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, (const float2*)kspace, c->coiltmp));
+        HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, x));
+      }
+      HIPCHK(c, fk.join());
+    }
     for (float2* b : {c->bx, c->by, c->bw, c->ux, c->uy, c->uw})
       HIPCHK(c, launch_fill(c->stream, b, c->img_total, make_float2(0.f, 0.f)));
     bool q_valid = false;
@@ -787,13 +874,10 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
         if (rc > 0) rc_all = rc;
         if (pcg_iters)
           for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
-        rc = enq_shrinks(c, x);
+        rc = enq_shrinks(c, x, ji == n_inner - 1);
         if (rc) return rc;
-        q_valid = false;
+        q_valid = true;  // the shrinks left A x = b - r in q
       }
-      int rc = enq_outer(c, x);
-      if (rc) return rc;
-      q_valid = true;
     }
     if (!graph_now) {
       HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1048,9 +1132,14 @@ int pics_features(pics_ctx* c, const float* khat, float* features) {
   if (!c || !khat || !features) return PICS_ERR_INVALID;
   for (const SliceDev& sd : c->sl)
     if (sd.m % kNetGrid || sd.n % kNetGrid) return fail(c, PICS_ERR_UNSUPPORTED, "features need m, n multiples of 64");
-  for (auto& g : c->groups)
-    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 2, c->sens, c->coiltmp));
-  for (auto& g : c->groups) HIPCHK(c, launch_col_coil_energy(make_launch(c, g), ws_for(c, g), c->coiltmp, c->ftmp));
+  {
+    GroupFork fk(c);
+    for (auto& g : c->groups) {
+      HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 2, c->sens, c->coiltmp));
+      HIPCHK(c, launch_col_coil_energy(make_launch(c, g), ws_for(c, g), c->coiltmp, c->ftmp));
+    }
+    HIPCHK(c, fk.join());
+  }
   HIPCHK(c, launch_features(c->stream, make_ws(c), c->nslices, c->ftmp, khat, features));
   return PICS_OK;
 }
@@ -1194,7 +1283,7 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
       if (rc) return rc;
       auto run = [&]() {
         return launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, c->pk, 0.0, c->p, nullptr,
-                                nullptr, nullptr, c->q, nullptr, nullptr, G, c->dpart, c->img_total);
+                                nullptr, nullptr, c->q, G, c->dpart, c->img_total);
       };
       for (int k = 0; k < 2; ++k) HIPCHK(c, run());
       HIPCHK(c, hipEventRecord(e0, c->stream));

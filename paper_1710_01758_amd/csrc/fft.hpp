@@ -197,8 +197,11 @@ struct RowLay {
   static __device__ __forceinline__ int addr(int idx, int seq) { return seq * stride + idx + (idx >> 4); }
 };
 
-template <int N, int NT, int DIR, int Ns, class Lay, int R, int... Rest>
-__device__ __forceinline__ void fft_stages(float2 (&v)[N / NT], int t, float2* lds, int seq,
+// DUAL: exchanges alternate between lds and lds_next and the barrier after
+// each exchange's reads is left out (the next exchange writes the other
+// buffer; the one after that is ordered by the next exchange's barrier).
+template <int N, int NT, int DIR, int Ns, class Lay, bool DUAL, int R, int... Rest>
+__device__ __forceinline__ void fft_stages(float2 (&v)[N / NT], int t, float2* lds, float2* lds_next, int seq,
                                            const float2* __restrict__ tw) {
   constexpr int E = N / NT;
   constexpr int Q = E / R;
@@ -234,23 +237,47 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[N / NT], int t, float2* l
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = lds[Lay::addr(t + NT * e, seq)];
-    __syncthreads();
-    fft_stages<N, NT, DIR, Ns * R, Lay, Rest...>(v, t, lds, seq, tw);
+    if constexpr (DUAL) {
+      fft_stages<N, NT, DIR, Ns * R, Lay, DUAL, Rest...>(v, t, lds_next, lds, seq, tw);
+    } else {
+      __syncthreads();
+      fft_stages<N, NT, DIR, Ns * R, Lay, DUAL, Rest...>(v, t, lds, lds, seq, tw);
+    }
   }
 }
 
-template <int N, int DIR, class Lay, int... Rs>
+template <class R>
+struct RadixCount;
+template <int... Rs>
+struct RadixCount<Radices<Rs...>> { static constexpr int value = sizeof...(Rs); };
+// LDS exchanges of one transform of length N (stages - 1)
+template <int N>
+constexpr int kExchanges = RadixCount<typename Plan<N>::R>::value - 1;
+
+template <int N, int DIR, class Lay, bool DUAL, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[N / Plan<N>::NT], int t, float2* lds,
-                                        int seq, const float2* __restrict__ tw) {
-  fft_stages<N, Plan<N>::NT, DIR, 1, Lay, Rs...>(v, t, lds, seq, tw);
+                                        float2* lds_next, int seq, const float2* __restrict__ tw) {
+  fft_stages<N, Plan<N>::NT, DIR, 1, Lay, DUAL, Rs...>(v, t, lds, lds_next, seq, tw);
 }
 
 // In-place transform of the cyclic registers.  Every thread of the block must
-// call it (it contains barriers).  `tw` points at this length's table.
+// call it (it contains barriers).  `tw` points at this length's table.  The
+// LDS buffer may be reused as soon as it returns.
 template <int N, int DIR, class Lay>
 __device__ __forceinline__ void fft(float2 (&v)[N / Plan<N>::NT], int t, float2* lds, int seq,
                                     const float2* __restrict__ tw) {
-  fft_run<N, DIR, Lay>(typename Plan<N>::R{}, v, t, lds, seq, tw);
+  fft_run<N, DIR, Lay, false>(typename Plan<N>::R{}, v, t, lds, lds, seq, tw);
+}
+
+// Same transform with its exchanges alternating between two LDS buffers,
+// first `lds_a`.  A caller chaining transforms keeps the alternation going
+// (the next transform starts on the buffer after the last one used: b when
+// kExchanges<N> is odd); the last exchange's buffer must not be written
+// before another barrier.
+template <int N, int DIR, class Lay>
+__device__ __forceinline__ void fft_dual(float2 (&v)[N / Plan<N>::NT], int t, float2* lds_a, float2* lds_b,
+                                         int seq, const float2* __restrict__ tw) {
+  fft_run<N, DIR, Lay, true>(typename Plan<N>::R{}, v, t, lds_a, lds_b, seq, tw);
 }
 
 }  // namespace pics

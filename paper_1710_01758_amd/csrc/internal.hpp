@@ -60,7 +60,7 @@ __device__ __forceinline__ double part_sum(const double* p, int count) {
 enum { PK_NONE = 0, PK_JACOBI = 1, PK_CIRC = 2, PK_LEARNED = 3 };
 
 // column-tile apply modes
-enum { CA_APPLY = 0, CA_PCG = 1, CA_OUTER = 2 };
+enum { CA_APPLY = 0, CA_PCG = 1 };
 // apply phases: one fused pass, or per-coil-group partial data terms + finish
 enum { AP_FUSED = 0, AP_PART = 1, AP_FIN = 2 };
 // apply term flags
@@ -90,12 +90,25 @@ struct WaveArgs {
 };
 
 // Fused TV shrink/update carried by the level-0 wavelet analysis.
+// Image-domain outer update fused into the shrink kernels (level 0):
+// mode 1: q = b - r (= A x after the solve that produced r);
+// mode 2: also g <- g + g1 - A_data x with A_data x = q - lam L x - gam x.
+struct OuterArgs {
+  int mode;
+  const float2* b;
+  const float2* r;
+  float2* q;
+  float2* g;
+  const float2* g1;
+};
+
 struct TvArgs {
   int enabled;
   float2* bx;
   float2* by;
   float2* ux;
   float2* uy;
+  OuterArgs outer;
 };
 
 struct Simple {
@@ -112,8 +125,7 @@ bool fft_size_supported(int N);
 // and adds them in a second pass.
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            float2* g, const float2* g1, int ngroups = 1, float2* dpart = nullptr,
-                            long long dstride = 0);
+                            int ngroups = 1, float2* dpart = nullptr, long long dstride = 0);
 hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, const float2* b, const float2* q,
                              float2* x, float2* r, const float2* pn, float2* p, float2* t);
 hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t);
@@ -128,8 +140,8 @@ hipError_t launch_col_coil_energy(const Launch& L, const Ws& w, const float2* co
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit, const int* maxit_per_slice);
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
-hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const float2* x, float2* bx,
-                            float2* by, float2* ux, float2* uy, float2* bw, float2* uw);
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,
+                            float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw);
 hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, const float2* ux, const float2* uy,
                                 const float2* uw, float2* rhs);
 // one wavelet level (analysis or synthesis per a.inverse); `tiles` = max over

@@ -11,13 +11,21 @@
 
 namespace pics {
 
-template <int M>
+template <int M, class P = Plan<M>>
 struct ColCfg {
-  static constexpr int NT = Plan<M>::NT;
+  static constexpr int NT = P::NT;
   static constexpr int E = M / NT;
   static constexpr int T = kColT;
   static constexpr int THREADS = NT * T;
 };
+
+// The fused operator's column tiles; lengths up to 256 give each transform
+// exchange its own LDS buffer (two buffers used in turn, so a barrier after
+// reading an exchange is not needed).
+template <int M>
+using ApplyCfg = ColCfg<M>;
+template <int M>
+struct ApplyDual { static constexpr bool value = M <= 256; };
 template <int N>
 struct RowCfg {
   static constexpr int NT = Plan<N>::NT;
@@ -75,7 +83,6 @@ __device__ __forceinline__ void stage_twiddles(float2* s_tw, const float2* __res
 // MODE CA_APPLY  p = xin
 //      CA_PCG    p = zs + beta p_old (beta from the rho partials), written to pn;
 //                sigma = Re(p^H A p) partial
-//      CA_OUTER  p = xin; also g <- g + g1 - (data term)
 // PH AP_FUSED  everything in one launch
 //    AP_PART   grid.z = ngroups workgroups per column tile; group z takes coils
 //              z, z + ngroups, ... and writes its partial data term to
@@ -84,14 +91,15 @@ __device__ __forceinline__ void stage_twiddles(float2* s_tw, const float2* __res
 //              and the mode's outputs (CA_PCG reads p back from pn)
 // ----------------------------------------------------------------------------
 template <int M, int MODE, int PH>
-__global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
+__global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
     Ws w, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
-    const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, float2* __restrict__ g,
-    const float2* __restrict__ g1, int ngroups, float2* __restrict__ dpart, long long dstride) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT, TH = ColCfg<M>::THREADS;
+    const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, int ngroups,
+    float2* __restrict__ dpart, long long dstride) {
+  constexpr int NT = ApplyCfg<M>::NT, E = ApplyCfg<M>::E, T = kColT, TH = ApplyCfg<M>::THREADS;
   constexpr int TS = T + 2;  // tile stride with the two halo columns
   constexpr int HP = (2 * M + TH - 1) / TH;
-  __shared__ float2 lds[M * TS];
+  constexpr bool DUAL = ApplyDual<M>::value;
+  __shared__ float2 lds[DUAL ? 2 * M * T : M * TS];
   __shared__ float2 s_tw[M];
   __shared__ double red[16];
   const int s = w.group[blockIdx.y];
@@ -219,10 +227,19 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
       float2 v[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = cmul(sv[e], pv[e]);
-      fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
+      if constexpr (DUAL) {
+        // exchanges alternate between the two buffers across both transforms
+        constexpr bool odd = (kExchanges<M> & 1) != 0;
+        fft_dual<M, -1, ColLay<T>>(v, t, lds, lds + M * T, j, s_tw);
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ((mbits >> e) & 1u) ? inv_m : 0.f);
-      fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
+        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ((mbits >> e) & 1u) ? inv_m : 0.f);
+        fft_dual<M, +1, ColLay<T>>(v, t, odd ? lds + M * T : lds, odd ? lds : lds + M * T, j, s_tw);
+      } else {
+        fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ((mbits >> e) & 1u) ? inv_m : 0.f);
+        fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
+      }
 #pragma unroll
       for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(sv[e], v[e]));
 #pragma unroll
@@ -265,27 +282,10 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_apply(
 
   float2* __restrict__ o = out + sd.img;
   double sig = 0.0;
-  if (MODE == CA_OUTER) {
-    float2* __restrict__ gg = g + sd.img;
-    const float2* __restrict__ g1s = g1 + sd.img;
-    float2 gv[E], g1v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      gv[e] = gg[(t + NT * e) * n + col];
-      g1v[e] = g1s[(t + NT * e) * n + col];
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int off = (t + NT * e) * n + col;
-      o[off] = q[e];
-      gg[off] = make_float2(gv[e].x + g1v[e].x - mu * acc[e].x, gv[e].y + g1v[e].y - mu * acc[e].y);
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      o[(t + NT * e) * n + col] = q[e];
-      sig += (double)pv[e].x * (double)q[e].x + (double)pv[e].y * (double)q[e].y;
-    }
+  for (int e = 0; e < E; ++e) {
+    o[(t + NT * e) * n + col] = q[e];
+    sig += (double)pv[e].x * (double)q[e].x + (double)pv[e].y * (double)q[e].y;
   }
   if (MODE == CA_PCG) {
     sig = block_sum_f64(sig, red);
@@ -658,39 +658,36 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, co
 template <int M, int PH>
 void launch_col_apply_phase(dim3 grid, const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            float2* g, const float2* g1, int ngroups, float2* dpart, long long dstride) {
-  const dim3 block(ColCfg<M>::THREADS);
+                            int ngroups, float2* dpart, long long dstride) {
+  const dim3 block(ApplyCfg<M>::THREADS);
   if (mode == CA_PCG)
     hipLaunchKernelGGL((k_col_apply<M, CA_PCG, PH>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc, pold,
-                       pn, out, g, g1, ngroups, dpart, dstride);
-  else if (mode == CA_OUTER && PH != AP_PART)  // the partial pass of CA_OUTER is CA_APPLY's
-    hipLaunchKernelGGL((k_col_apply<M, PH == AP_PART ? CA_APPLY : CA_OUTER, PH>), grid, block, 0, L.stream, w, terms,
-                       pk, tol, xin, zsrc, pold, pn, out, g, g1, ngroups, dpart, dstride);
+                       pn, out, ngroups, dpart, dstride);
   else
     hipLaunchKernelGGL((k_col_apply<M, CA_APPLY, PH>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc, pold,
-                       pn, out, g, g1, ngroups, dpart, dstride);
+                       pn, out, ngroups, dpart, dstride);
 }
 
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            float2* g, const float2* g1, int ngroups, float2* dpart, long long dstride) {
+                            int ngroups, float2* dpart, long long dstride) {
   const int split = (ngroups > 1 && (terms & TERM_DATA)) ? ngroups : 1;
   if (split > 1 && !dpart) return hipErrorInvalidValue;
   const dim3 grid(L.n / kColT, L.count);
   switch (L.m) {
-#define PICS_CASE(M)                                                                                              \
-  case M:                                                                                                         \
-    if (split == 1) {                                                                                             \
-      launch_col_apply_phase<M, AP_FUSED>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, g, g1, 1,   \
-                                          dpart, dstride);                                                       \
-    } else {                                                                                                      \
-      launch_col_apply_phase<M, AP_PART>(dim3(grid.x, grid.y, split), L, w, mode, terms, pk, tol, xin, zsrc,      \
-                                         pold, pn, out, g, g1, split, dpart, dstride);                           \
-      const hipError_t e = hipGetLastError();                                                                     \
-      if (e != hipSuccess) return e;                                                                              \
-      launch_col_apply_phase<M, AP_FIN>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, g, g1, split, \
-                                        dpart, dstride);                                                         \
-    }                                                                                                             \
+#define PICS_CASE(M)                                                                                            \
+  case M:                                                                                                       \
+    if (split == 1) {                                                                                           \
+      launch_col_apply_phase<M, AP_FUSED>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, 1, dpart, \
+                                          dstride);                                                            \
+    } else {                                                                                                    \
+      launch_col_apply_phase<M, AP_PART>(dim3(grid.x, grid.y, split), L, w, mode, terms, pk, tol, xin, zsrc,    \
+                                         pold, pn, out, split, dpart, dstride);                                \
+      const hipError_t e = hipGetLastError();                                                                   \
+      if (e != hipSuccess) return e;                                                                            \
+      launch_col_apply_phase<M, AP_FIN>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, split,      \
+                                        dpart, dstride);                                                       \
+    }                                                                                                           \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE

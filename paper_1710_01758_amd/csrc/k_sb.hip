@@ -97,12 +97,28 @@ __global__ void k_set_int(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// --------------------------------------------------- outer update (fused)
+// After a PCG solve, A x = b - r exactly in exact arithmetic (r is the
+// solver's residual), so the next solve's A x0 and the data term of the outer
+// update (Algorithm 1 steps 13-15, image-domain form)
+//   A_data x = A x - lam (D_x^H D_x + D_y^H D_y) x - gam x
+// need no further operator application.  lap = 4 x - (four neighbours).
+__device__ __forceinline__ void outer_at(const SliceDev& sd, const OuterArgs& oa, long long pp, float2 xc,
+                                         float2 lap, float2 bv, float2 rv, float2 gv, float2 g1v) {
+  const float2 ax = csub(bv, rv);
+  oa.q[pp] = ax;
+  if (oa.mode == 2) {
+    const float2 ad = make_float2(ax.x - sd.lam * lap.x - sd.gam * xc.x, ax.y - sd.lam * lap.y - sd.gam * xc.y);
+    oa.g[pp] = make_float2(gv.x + g1v.x - ad.x, gv.y + g1v.y - ad.y);
+  }
+}
+
 // ------------------------------------------------------- TV shrink/update
 // D_x x = x[i,j] - x[i-1,j], D_y x = x[i,j] - x[i,j-1] (periodic);
 // v = D x + b;  d = shrink(v, 1/lam);  b <- v - d;  u = d - b (the next
 // right-hand side uses D^H u).  With no wavelet the same is done on x itself
 // with threshold 1/gam.
-__global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, const float2* __restrict__ x,
+__global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, OuterArgs oa, const float2* __restrict__ x,
                                                    float2* __restrict__ bx, float2* __restrict__ by,
                                                    float2* __restrict__ ux, float2* __restrict__ uy,
                                                    float2* __restrict__ bw, float2* __restrict__ uw) {
@@ -118,6 +134,14 @@ __global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, con
     const float2 xc = x[o + p];
     const float2 xu = x[o + (long long)((i - 1 + m) % m) * n + j];
     const float2 xl = x[o + (long long)i * n + (j - 1 + n) % n];
+    if (oa.mode) {
+      const float2 xd = x[o + (long long)((i + 1) % m) * n + j];
+      const float2 xr = x[o + (long long)i * n + (j + 1) % n];
+      const float2 lap = make_float2(4.f * xc.x - xu.x - xd.x - xl.x - xr.x, 4.f * xc.y - xu.y - xd.y - xl.y - xr.y);
+      const float2 gv = oa.mode == 2 ? oa.g[o + p] : make_float2(0.f, 0.f);
+      const float2 g1v = oa.mode == 2 ? oa.g1[o + p] : make_float2(0.f, 0.f);
+      outer_at(sd, oa, o + p, xc, lap, oa.b[o + p], oa.r[o + p], gv, g1v);
+    }
     {
       const float2 v = cadd(csub(xc, xu), bx[o + p]);
       const float2 d = shrink(v, tl);
@@ -185,11 +209,12 @@ __device__ __forceinline__ float filt_g(int wavelet, int t) {
   return (t & 1) ? -v : v;
 }
 
-__device__ __forceinline__ void coef_out(const SliceDev& sd, const WaveArgs& a, long long pos, float2 c) {
+// bwv: a.bw[pos], loaded by the caller (shrink mode only)
+__device__ __forceinline__ void coef_out(const SliceDev& sd, const WaveArgs& a, long long pos, float2 c, float2 bwv) {
   if (a.mode == 0) {
     a.coef[pos] = c;
   } else {
-    const float2 v = cadd(c, a.bw[pos]);
+    const float2 v = cadd(c, bwv);
     const float2 d = shrink(v, 1.0f / sd.gam);
     const float2 b = csub(v, d);
     a.bw[pos] = b;
@@ -203,6 +228,7 @@ __device__ __forceinline__ void coef_out(const SliceDev& sd, const WaveArgs& a, 
 // column to the left for the fused TV step), all with periodic wrap.
 constexpr int kWT = 16;
 constexpr int kWIn = 2 * kWT + 7;  // 39: 1 TV halo + 2 kWT + 6 filter halo
+constexpr int kWThreads = 256;     // workgroup size of both wavelet kernels
 
 template <int K>
 struct Filt {
@@ -235,10 +261,24 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
   const bool lastlev = (a.level == sd.levels - 1);
   const bool small = ml < kWIn || nl < kWIn;
   const Filt<K> f;
-  for (int idx = threadIdx.x; idx < kWIn * kWIn; idx += blockDim.x) {
-    const int ra = idx / kWIn, cb = idx % kWIn;
-    const int r = wrap(2 * k0 - 1 + ra, ml, small), c = wrap(2 * c0 - 1 + cb, nl, small);
-    tile[ra][cb] = a.in[o + (long long)r * n + c];
+  {
+    // every load of the thread in flight at once, then the LDS stores
+    constexpr int PER = (kWIn * kWIn + kWThreads - 1) / kWThreads;
+    float2 v[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      if (idx < kWIn * kWIn) {
+        const int ra = idx / kWIn, cb = idx % kWIn;
+        const int r = wrap(2 * k0 - 1 + ra, ml, small), c = wrap(2 * c0 - 1 + cb, nl, small);
+        v[e] = a.in[o + (long long)r * n + c];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      if (idx < kWIn * kWIn) tile[idx / kWIn][idx % kWIn] = v[e];
+    }
   }
   __syncthreads();
   // along axis 1
@@ -256,7 +296,25 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
   }
   __syncthreads();
   // along axis 0, then the band placement (Mallat layout)
-  for (int idx = threadIdx.x; idx < kWT * 2 * kWT; idx += blockDim.x) {
+  constexpr int PER = kWT * 2 * kWT / kWThreads;
+  float2 blo[PER] = {}, bhi[PER] = {};  // Bregman variables of the outputs (shrink mode), loaded up front
+  if (a.mode == 1) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      const int k = idx / (2 * kWT), cp = idx % (2 * kWT);
+      const int half = cp / kWT, gk = k0 + k, gc = c0 + (cp % kWT);
+      if (gk < mh && gc < nh) {
+        const long long plo = o + (long long)gk * n + half * nh + gc;
+        const long long phi = o + (long long)(mh + gk) * n + half * nh + gc;
+        if (!(half == 0 && !lastlev)) blo[e] = a.bw[plo];
+        bhi[e] = a.bw[phi];
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int idx = threadIdx.x + kWThreads * e;
     const int k = idx / (2 * kWT), cp = idx % (2 * kWT);
     const int half = cp / kWT, gk = k0 + k, gc = c0 + (cp % kWT);
     if (gk >= mh || gc >= nh) continue;
@@ -270,19 +328,48 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
     const long long plo = o + (long long)gk * n + half * nh + gc;
     const long long phi = o + (long long)(mh + gk) * n + half * nh + gc;
     if (half == 0 && !lastlev) a.out[plo] = lo;  // approximation block feeds the next level
-    else coef_out(sd, a, plo, lo);
-    coef_out(sd, a, phi, hi);
+    else coef_out(sd, a, plo, lo, blo[e]);
+    coef_out(sd, a, phi, hi, bhi[e]);
   }
   // level 0: Algorithm 1 steps 6, 7, 9, 10 on the 2 kWT x 2 kWT pixel block
   if (tv.enabled && a.level == 0) {
     const float thr = 1.0f / sd.lam;
-    for (int idx = threadIdx.x; idx < 4 * kWT * kWT; idx += blockDim.x) {
+    constexpr int PER = 4 * kWT * kWT / kWThreads;
+    const OuterArgs& oa = tv.outer;
+    float2 bxs[PER], bys[PER], obs[PER], ors[PER], ogs[PER] = {}, og1s[PER] = {};
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
+      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+      if (i < ml && jj < nl) {
+        const long long pp = o + (long long)i * n + jj;
+        bxs[e] = tv.bx[pp];
+        bys[e] = tv.by[pp];
+        if (oa.mode) {
+          obs[e] = oa.b[pp];
+          ors[e] = oa.r[pp];
+          if (oa.mode == 2) {
+            ogs[e] = oa.g[pp];
+            og1s[e] = oa.g1[pp];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
       const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
       const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
       if (i >= ml || jj >= nl) continue;
       const long long pp = o + (long long)i * n + jj;
       const float2 xc = tile[1 + ia][1 + jb], xu = tile[ia][1 + jb], xl = tile[1 + ia][jb];
-      const float2 bxv = tv.bx[pp], byv = tv.by[pp];
+      const float2 bxv = bxs[e], byv = bys[e];
+      if (oa.mode) {
+        const float2 xd = tile[2 + ia][1 + jb], xr = tile[1 + ia][2 + jb];
+        const float2 lap = make_float2(4.f * xc.x - xu.x - xd.x - xl.x - xr.x, 4.f * xc.y - xu.y - xd.y - xl.y - xr.y);
+        outer_at(sd, oa, pp, xc, lap, obs[e], ors[e], ogs[e], og1s[e]);
+      }
       {
         const float2 v = cadd(csub(xc, xu), bxv);
         const float2 d = shrink(v, thr);
@@ -329,12 +416,26 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
   const bool lastlev = (a.level == sd.levels - 1);
   const bool small = mh < kWB || nh < kWB;
   const Filt<K> f;
-  for (int idx = threadIdx.x; idx < 4 * kWB * kWB; idx += blockDim.x) {
-    const int b = idx / (kWB * kWB), rr = (idx / kWB) % kWB, cc = idx % kWB;
-    const int a0 = b >> 1, a1 = b & 1;
-    const int kr = wrap(k0 - 3 + rr, mh, small), kc = wrap(c0 - 3 + cc, nh, small);
-    const float2* src = (a0 == 0 && a1 == 0 && !lastlev) ? a.in : a.coef;
-    bands[b][rr][cc] = src[o + (long long)(a0 * mh + kr) * n + a1 * nh + kc];
+  {
+    constexpr int NB = 4 * kWB * kWB;
+    constexpr int PER = (NB + kWThreads - 1) / kWThreads;
+    float2 v[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      if (idx < NB) {
+        const int b = idx / (kWB * kWB), rr = (idx / kWB) % kWB, cc = idx % kWB;
+        const int a0 = b >> 1, a1 = b & 1;
+        const int kr = wrap(k0 - 3 + rr, mh, small), kc = wrap(c0 - 3 + cc, nh, small);
+        const float2* src = (a0 == 0 && a1 == 0 && !lastlev) ? a.in : a.coef;
+        v[e] = src[o + (long long)(a0 * mh + kr) * n + a1 * nh + kc];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      if (idx < NB) bands[idx / (kWB * kWB)][(idx / kWB) % kWB][idx % kWB] = v[e];
+    }
   }
   __syncthreads();
   // along axis 0
@@ -355,7 +456,28 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
   }
   __syncthreads();
   // along axis 1
-  for (int idx = threadIdx.x; idx < 4 * kWT * kWT; idx += blockDim.x) {
+  constexpr int PER = 4 * kWT * kWT / kWThreads;
+  const bool rhs_mode = a.level == 0 && a.mode == 1;
+  float2 rg[PER], rx0[PER], rx1[PER], ry0[PER], ry1[PER];  // right-hand-side operands, loaded up front
+  if (rhs_mode) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
+      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+      if (i < ml && jj < nl) {
+        const long long p = o + (long long)i * n + jj;
+        rg[e] = a.g[p];
+        rx0[e] = a.ux[p];
+        rx1[e] = a.ux[o + (long long)((i + 1) % sd.m) * n + jj];
+        ry0[e] = a.uy[p];
+        ry1[e] = a.uy[o + (long long)i * n + (jj + 1) % n];
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int idx = threadIdx.x + kWThreads * e;
     const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
     const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
     if (i >= ml || jj >= nl) continue;
@@ -369,8 +491,14 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
       const float g = (jb & 1) ? f.g[2 * tt + 1] : f.g[2 * tt];
       acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
     }
-    if (a.level == 0 && a.mode == 1) a.rhs[o + (long long)i * n + jj] = rhs_at(sd, o, i, jj, a.g, a.ux, a.uy, acc);
-    else a.out[o + (long long)i * n + jj] = acc;
+    if (rhs_mode) {
+      // Algorithm 1 step 4: g + lam (D_x^H u_x + D_y^H u_y) + gam W^H u_w
+      const float2 dx = csub(rx0[e], rx1[e]), dy = csub(ry0[e], ry1[e]);
+      a.rhs[o + (long long)i * n + jj] = make_float2(rg[e].x + sd.lam * (dx.x + dy.x) + sd.gam * acc.x,
+                                                     rg[e].y + sd.lam * (dx.y + dy.y) + sd.gam * acc.y);
+    } else {
+      a.out[o + (long long)i * n + jj] = acc;
+    }
   }
 }
 
@@ -485,10 +613,10 @@ hipError_t launch_set_int(hipStream_t st, int* p, int v) {
   return hipGetLastError();
 }
 
-hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const float2* x, float2* bx,
-                            float2* by, float2* ux, float2* uy, float2* bw, float2* uw) {
-  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, only_nowavelet, x, bx, by, ux, uy, bw,
-                     uw);
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,
+                            float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw) {
+  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, only_nowavelet, oa, x, bx, by, ux, uy,
+                     bw, uw);
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ def test_binding_constants_match_header():
     assert d["PICS_OPT_POLL_CHUNK"] == B.OPT_POLL_CHUNK
     assert d["PICS_OPT_GRAPH_BUDGET"] == B.OPT_GRAPH_BUDGET
     assert d["PICS_OPT_COIL_GROUPS"] == B.OPT_COIL_GROUPS
+    assert d["PICS_OPT_CONCURRENT_GROUPS"] == B.OPT_CONCURRENT_GROUPS
     assert d["PICS_TUNE_FORCE"] == B.TUNE_FORCE
     assert d["PICS_TUNE_NO_WRITE"] == B.TUNE_NO_WRITE
 

@@ -427,3 +427,31 @@ def test_autotune_picks_a_valid_split(torch, B, tmp_path, monkeypatch):
         s = it.spec
         ref = ops.apply_A(x, it.sens, it.mask2d.astype(np.float64), s.mu, s.lam, s.gam)
         assert H.rel_err(g, ref) < 1e-5
+
+
+def test_concurrent_size_groups_equal_serial(torch, B):
+    """Per-size-group kernels on side streams give bitwise the results of
+    running the groups one after the other (apply_A, M^-1, FFT, Split Bregman
+    with graph replay)."""
+    _say("concurrent size groups == serial")
+    specs = gen.cfg4_specs(nslices=8)
+    insts = [_inst(sp, 6000 + i) for i, sp in enumerate(specs)]
+    assert len({(s.m, s.n) for s in specs}) > 1
+    outs = []
+    for conc in (0, 1):
+        ctx, ksp = _ctx(B, insts)
+        ctx.set_option(B.OPT_CONCURRENT_GROUPS, conc)
+        ctx.build_preconditioner("circulant")
+        xs = [gen.random_image(700 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
+        xd = B.to_device(B.pack_images(xs))
+        ya, ym, yf = torch.empty_like(xd), torch.empty_like(xd), torch.empty_like(xd)
+        ctx.apply_A(xd, ya)
+        ctx.apply_Minv(xd, ym)
+        ctx.fft2(xd, yf)
+        x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+        it, _ = ctx.split_bregman_recon(ksp, x, n_outer=5, tol=1e-3, maxit=1000)
+        torch.cuda.synchronize()
+        outs.append([_host(ya), _host(ym), _host(yf), _host(x), it])
+        ctx.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
