@@ -161,11 +161,11 @@ int split_bregman_recon(pics_ctx* ctx, const void* kspace, int32_t n_outer, int3
  * PICS_OPT_POLL_CHUNK: PCG iterations enqueued between host convergence polls
  *   (first poll; later polls double it, up to 32).  Default 2.
  * PICS_OPT_GRAPH_BUDGET: split_bregman_recon runs the first outer iteration
- *   host-polled and replays the others from one captured HIP graph whose PCG
- *   solves carry this many iterations (kernels of converged slices exit at
- *   entry).  If a solve needs more, the reconstruction is redone host-polled,
- *   so results never depend on the budget; the budget is then raised.
- *   0 disables the graph.  Default 2.
+ *   host-polled and the others from one captured HIP graph whose PCG solves
+ *   carry this many iterations (kernels of converged slices exit at entry).
+ *   If a solve needs more, the reconstruction is redone host-polled, so
+ *   results never depend on the budget; the context then raises its budget
+ *   (to 2, then doubling).  0 disables the graph.  Default 1.
  * PICS_OPT_COIL_GROUPS: split every column tile's coil loop over this many
  *   workgroups (clamped to each group's coil count), overriding the
  *   autotuner; 1 = no split (the default before pics_autotune).

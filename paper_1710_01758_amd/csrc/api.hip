@@ -63,7 +63,7 @@ struct pics_ctx {
   std::string err;
 
   // Split Bregman outer iterations replayed from a captured graph
-  int graph_budget = 2;          // PCG iterations per solve inside the graph (0: host-polled only)
+  int graph_budget = 1;          // PCG iterations per solve inside the graph (0: host-polled only)
   int* solve_counter = nullptr;  // device: history row of the next solve
   int* hist = nullptr;           // device: [solves][nslices] iterations, then [solves][nslices] status
   long long hist_cap = 0;
@@ -73,12 +73,12 @@ struct pics_ctx {
   struct GraphKey {
     const void* x;
     double tol;
-    int budget, pk, n_inner;
+    int budget, pk, n_inner, n_rep;
     const int* hist;
     int tuning;  // tuning generation: a new coil split or workspace needs a new graph
     bool operator==(const GraphKey& o) const {
-      return x == o.x && tol == o.tol && budget == o.budget && pk == o.pk && n_inner == o.n_inner && hist == o.hist &&
-             tuning == o.tuning;
+      return x == o.x && tol == o.tol && budget == o.budget && pk == o.pk && n_inner == o.n_inner &&
+             n_rep == o.n_rep && hist == o.hist && tuning == o.tuning;
     }
   } graph_key{};
   int graph_fallbacks = 0;       // solves that exceeded the budget (reconstruction redone host-polled)
@@ -601,7 +601,6 @@ int enq_pcg_setup(pics_ctx* c, const float2* b, float2* x, double tol, int maxit
   const Ws w = make_ws(c);
   const int pk = c->pk;
   const bool circ = pk == PK_CIRC || pk == PK_LEARNED;
-  HIPCHK(c, launch_pcg_reset(c->stream, w, c->nslices, maxit, maxit_dev));
   {
     GroupFork fk(c);
     for (auto& g : c->groups) {
@@ -609,7 +608,7 @@ int enq_pcg_setup(pics_ctx* c, const float2* b, float2* x, double tol, int maxit
         HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr,
                                    nullptr, c->q, g.coil_groups, c->dpart, c->img_total));
       HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
-                                  c->t));
+                                  c->t, maxit, maxit_dev));
     }
     HIPCHK(c, fk.join());
   }
@@ -751,16 +750,18 @@ int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner
     if (rc) return rc;
     rc = enq_pcg_iters(c, x, tol, 0, budget);
     if (rc) return rc;
-    HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 0, x));
-    HIPCHK(c, launch_pcg_record(c->stream, w, c->nslices, c->hist, c->hist + c->hist_cap / 2, c->solve_counter));
+    HIPCHK(c, launch_pcg_finish(c->stream, w, c->nslices, tol, c->hist, c->hist + c->hist_cap / 2,
+                                c->solve_counter));
     rc = enq_shrinks(c, x, ji == n_inner - 1);
     if (rc) return rc;
   }
   return PICS_OK;
 }
 
-int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
-  const pics_ctx::GraphKey key{x, tol, budget, c->pk, n_inner, c->hist, c->tuning_gen};
+// Capture n_rep outer iterations (all but the first of a reconstruction) as
+// one graph.
+int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget, int n_rep) {
+  const pics_ctx::GraphKey key{x, tol, budget, c->pk, n_inner, n_rep, c->hist, c->tuning_gen};
   if (c->graph_exec && c->graph_key == key) return PICS_OK;
   if (c->graph_exec) {
     HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
@@ -772,7 +773,8 @@ int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
   int rc;
   {
     StreamSwap sw(c, c->cap_stream);
-    rc = enq_outer_iteration_budgeted(c, x, tol, n_inner, budget);
+    rc = PICS_OK;
+    for (int k = 0; k < n_rep && rc == PICS_OK; ++k) rc = enq_outer_iteration_budgeted(c, x, tol, n_inner, budget);
   }
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
   if (rc) {
@@ -885,10 +887,10 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
     }
     // outer iterations 2 .. n_outer from the captured graph
     const int budget = std::min(c->graph_budget, maxit);
-    int rc = sb_graph(c, x, tol, n_inner, budget);
+    int rc = sb_graph(c, x, tol, n_inner, budget, n_outer - 1);
     if (rc) return rc;
     HIPCHK(c, launch_set_int(c->stream, c->solve_counter, n_inner));
-    for (int jo = 1; jo < n_outer; ++jo) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
     const long long rows = nsolve * c->nslices;
     c->hist_host.resize(2 * rows);
     HIPCHK(c, hipMemcpyAsync(c->hist_host.data(), c->hist, sizeof(int) * rows, hipMemcpyDeviceToHost, c->stream));
@@ -909,7 +911,7 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
     // a solve needed more than the budget: redo the reconstruction host-polled
     int mx = 0;
     for (long long r = (long long)n_inner * c->nslices; r < rows; ++r) mx = std::max(mx, c->hist_host[r]);
-    c->graph_budget = std::min(64, std::max(c->graph_budget * 2, mx + 2));
+    c->graph_budget = std::min(64, std::max(c->graph_budget < 2 ? 2 : c->graph_budget * 2, mx + 1));
     c->graph_fallbacks++;
   }
   return PICS_OK;

@@ -126,8 +126,11 @@ bool fft_size_supported(int N);
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
                             int ngroups = 1, float2* dpart = nullptr, long long dstride = 0);
+// RU_SETUP also resets the slices' PCG state (iteration limit maxit, or
+// maxit_ps[slice] when given)
 hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, const float2* b, const float2* q,
-                             float2* x, float2* r, const float2* pn, float2* p, float2* t);
+                             float2* x, float2* r, const float2* pn, float2* p, float2* t, int maxit = 0,
+                             const int* maxit_ps = nullptr);
 hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t);
 hipError_t launch_row_z(const Launch& L, const Ws& w, const float2* t, const float2* r, float2* z);
 hipError_t launch_row_fft(const Launch& L, const Ws& w, int inverse, int ncoil_mode, const float2* in, float2* out);
@@ -138,7 +141,6 @@ hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, flo
 hipError_t launch_col_coil_energy(const Launch& L, const Ws& w, const float2* coil_rows, float* energy);
 
 // ---- per-pixel kernels (k_sb.hip)
-hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit, const int* maxit_per_slice);
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
 hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,
                             float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw);
@@ -152,8 +154,10 @@ hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, cons
                           float* kinv, float* jac, int* bad);
 hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v);
 hipError_t launch_add_gamma(const Simple& S, const Ws& w, const float2* wx, const float2* x, float2* y);
-hipError_t launch_pcg_record(hipStream_t st, const Ws& w, int nslices, int* hist_iters, int* hist_status,
-                             int* counter);
+// end-of-solve stop test of every slice, then the per-slice iteration count
+// and status recorded at history row *counter (the counter advances)
+hipError_t launch_pcg_finish(hipStream_t st, const Ws& w, int nslices, double tol, int* hist_iters,
+                             int* hist_status, int* counter);
 hipError_t launch_set_int(hipStream_t st, int* p, int v);
 
 }  // namespace pics

@@ -309,7 +309,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
                                                                    const float2* __restrict__ b,
                                                                    const float2* __restrict__ q, float2* x, float2* r,
                                                                    const float2* __restrict__ pn, float2* p,
-                                                                   float2* __restrict__ tout) {
+                                                                   float2* __restrict__ tout, int maxit,
+                                                                   const int* __restrict__ maxit_ps) {
   constexpr int NT = RowCfg<N>::NT, E = RowCfg<N>::E;
   __shared__ float2 lds[RowCfg<N>::LDS];
   __shared__ float2 s_tw[N];
@@ -324,6 +325,19 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
 
   int it = 0;
   float alpha = 0.f;
+  if (mode == RU_SETUP && blockIdx.x == 0 && threadIdx.x == 0) {
+    // a new solve: reset the slice's PCG state (nothing reads it before the
+    // set-up's stop test, which follows this kernel)
+    PcgState ns;
+    ns.it_a = 0;
+    ns.it_r = 0;
+    ns.done = 0;
+    ns.status = 0;
+    ns.iters = 0;
+    ns.maxit = maxit_ps ? maxit_ps[s] : maxit;
+    ns.relres = 0.0;
+    *st = ns;
+  }
   if (mode == RU_UPDATE) {
     if (st->done) return;
     it = st->it_r;
@@ -698,13 +712,14 @@ hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, i
 }
 
 hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, const float2* b, const float2* q,
-                             float2* x, float2* r, const float2* pn, float2* p, float2* t) {
+                             float2* x, float2* r, const float2* pn, float2* p, float2* t, int maxit,
+                             const int* maxit_ps) {
   const dim3 grid(L.m / kRowRR, L.count);
   switch (L.n) {
 #define PICS_CASE(N)                                                                                      \
   case N:                                                                                                 \
     hipLaunchKernelGGL(k_row_update<N>, grid, dim3(RowCfg<N>::THREADS), 0, L.stream, w, mode, pk, b, q, x, \
-                       r, pn, p, t);                                                                      \
+                       r, pn, p, t, maxit, maxit_ps);                                                     \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE

@@ -27,18 +27,32 @@ __device__ __forceinline__ float2 shrink(float2 v, float thr) {
 
 // ------------------------------------------------------------ PCG control
 
-__global__ void k_pcg_reset(Ws w, int nslices, int maxit, const int* __restrict__ maxit_per_slice) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nslices) return;
-  PcgState st;
-  st.it_a = 0;
-  st.it_r = 0;
-  st.done = 0;
-  st.status = 0;
-  st.iters = 0;
-  st.maxit = maxit_per_slice ? maxit_per_slice[s] : maxit;
-  st.relres = 0.0;
-  w.st[s] = st;
+// Stop test of one slice: converged (status 1), iteration limit (0), or, at
+// the set-up, a zero right-hand side (converged, x = 0; returns true).
+__device__ __forceinline__ bool slice_stop_test(const Ws& w, int s, double tol, int setup) {
+  const SliceDev& sd = w.sl[s];
+  PcgState* st = w.st + s;
+  if (st->done) return false;
+  const int nrt = sd.m / kRowRR;
+  const double rr = part_sum(part_ptr(w.part, s, P_RR), nrt);
+  const double bb = part_sum(part_ptr(w.part, s, P_BB), nrt);
+  int status = -100;
+  bool zero_x = false;
+  if (setup && bb == 0.0) {
+    zero_x = true;
+    status = 1;
+  } else if (rr <= tol * tol * bb) {
+    status = 1;
+  } else if (st->it_a >= st->maxit) {
+    status = 0;
+  }
+  if (status != -100) {
+    st->done = 1;
+    st->status = status;
+    st->iters = st->it_a;
+    st->relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+  }
+  return zero_x;
 }
 
 // Stop test at the set-up and at host polling points.  A zero right-hand side
@@ -46,31 +60,8 @@ __global__ void k_pcg_reset(Ws w, int nslices, int maxit, const int* __restrict_
 __global__ __launch_bounds__(256) void k_pcg_check(Ws w, double tol, int setup, float2* __restrict__ x) {
   const int s = blockIdx.x;
   const SliceDev sd = w.sl[s];
-  PcgState* st = w.st + s;
   __shared__ int zero_x;
-  if (threadIdx.x == 0) {
-    zero_x = 0;
-    if (!st->done) {
-      const int nrt = sd.m / kRowRR;
-      const double rr = part_sum(part_ptr(w.part, s, P_RR), nrt);
-      const double bb = part_sum(part_ptr(w.part, s, P_BB), nrt);
-      int status = -100;
-      if (setup && bb == 0.0) {
-        zero_x = 1;
-        status = 1;
-      } else if (rr <= tol * tol * bb) {
-        status = 1;
-      } else if (st->it_a >= st->maxit) {
-        status = 0;
-      }
-      if (status != -100) {
-        st->done = 1;
-        st->status = status;
-        st->iters = st->it_a;
-        st->relres = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-      }
-    }
-  }
+  if (threadIdx.x == 0) zero_x = slice_stop_test(w, s, tol, setup) ? 1 : 0;
   __syncthreads();
   if (zero_x) {
     const long long np = (long long)sd.m * sd.n;
@@ -78,14 +69,16 @@ __global__ __launch_bounds__(256) void k_pcg_check(Ws w, double tol, int setup, 
   }
 }
 
-// Per-slice iteration count and status of the solve just finished, stored at
-// row *counter of the history; then the counter advances (graph replays).
-__global__ __launch_bounds__(256) void k_pcg_record(Ws w, int nslices, int* __restrict__ hist_iters,
+// End of a fixed-budget solve (graph replays): every slice's stop test, then
+// its iteration count and status stored at row *counter of the history; then
+// the counter advances.
+__global__ __launch_bounds__(256) void k_pcg_finish(Ws w, int nslices, double tol, int* __restrict__ hist_iters,
                                                     int* __restrict__ hist_status, int* __restrict__ counter) {
   __shared__ int row;
   if (threadIdx.x == 0) row = *counter;
   __syncthreads();
   for (int s = threadIdx.x; s < nslices; s += blockDim.x) {
+    slice_stop_test(w, s, tol, 0);
     hist_iters[(long long)row * nslices + s] = w.st[s].iters;
     hist_status[(long long)row * nslices + s] = w.st[s].status;
   }
@@ -592,19 +585,14 @@ static dim3 simple_grid(const Simple& S) {
   return dim3((unsigned)blocks, S.nslices);
 }
 
-hipError_t launch_pcg_reset(hipStream_t st, const Ws& w, int nslices, int maxit, const int* maxit_per_slice) {
-  hipLaunchKernelGGL(k_pcg_reset, dim3((nslices + 63) / 64), dim3(64), 0, st, w, nslices, maxit, maxit_per_slice);
-  return hipGetLastError();
-}
-
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x) {
   hipLaunchKernelGGL(k_pcg_check, dim3(nslices), dim3(256), 0, st, w, tol, setup, x);
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_record(hipStream_t st, const Ws& w, int nslices, int* hist_iters, int* hist_status,
-                             int* counter) {
-  hipLaunchKernelGGL(k_pcg_record, dim3(1), dim3(256), 0, st, w, nslices, hist_iters, hist_status, counter);
+hipError_t launch_pcg_finish(hipStream_t st, const Ws& w, int nslices, double tol, int* hist_iters,
+                             int* hist_status, int* counter) {
+  hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(256), 0, st, w, nslices, tol, hist_iters, hist_status, counter);
   return hipGetLastError();
 }
 
