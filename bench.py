@@ -153,6 +153,36 @@ def workload_section(torch, B, insts, label, steps=2):
                                "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": byts}}
 
 
+def param_sets_section(torch, B, nslices=8):
+    """PCG iterations per Bregman iteration for the paper's three parameter
+    sets with none / Jacobi / circulant at 256 x 256 x 12 (the structure of the
+    paper's Fig. 5): slice 0's per-solve counts, the batch-mean total over 20
+    Bregman iterations and the none / circulant gain, at the literal data scale
+    and at 1e3 (shrinks active)."""
+    out = {}
+    for scale in (1.0, 1e3):
+        rows = {}
+        for sid, (mu, lam, gam) in gen.PARAM_SETS.items():
+            spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, mu=mu, lam=lam, gam=gam,
+                                 data_scale=scale)
+            insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(nslices)]
+            ctx, ksp = B.context_for(insts)
+            row = {"mu": mu, "lambda": lam, "gamma": gam}
+            for kind in ("none", "jacobi", "circulant"):
+                ctx.build_preconditioner(kind)
+                x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+                it, _ = ctx.split_bregman_recon(ksp, x, n_outer=20, tol=1e-3, maxit=1000)
+                row[kind] = {"slice0_per_bregman_iteration": it[:, 0].tolist(),
+                             "mean_total": float(it.sum(axis=0).mean())}
+            row["gain_total"] = round(row["none"]["mean_total"] / row["circulant"]["mean_total"], 2)
+            row["gain_first"] = round(float(np.mean([row["none"]["slice0_per_bregman_iteration"][0]]))
+                                      / max(1, row["circulant"]["slice0_per_bregman_iteration"][0]), 2)
+            rows[f"set{sid}"] = row
+            ctx.close()
+        out[f"data_scale_{scale:g}"] = rows
+    return out
+
+
 def learned_section(torch, B, steps):
     """Train the spectrum correction on 2000 instances of the 64 x 64 x 4
     training distribution (random R in [2, 8], mu / lambda / gamma within a
@@ -204,7 +234,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip training / evaluating the learned correction")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 512^2 x 32 slice and the ragged batch")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 512^2 x 32 slice, the ragged batch and the parameter-set comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--mode", choices=["full", "apply"], default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs)")
@@ -315,6 +346,9 @@ def main():
         out["ragged_batch_64"] = workload_section(
             torch, B, [gen.make_instance(sp, gen.eval_seed(4, i)) for i, sp in enumerate(specs)],
             "64 slices {128^2, 192^2, 256x224, 320^2}, 8-32 coils, R in {3,4,6}, TV + db4 x3")
+    if not a.no_extra:
+        log("bench: parameter sets 1-3, none / Jacobi / circulant")
+        out["param_sets_256x256x12"] = param_sets_section(torch, B)
     if not a.no_learned:
         out["learned"] = learned_section(torch, B, a.train_steps)
     if not a.no_cpu_baseline:

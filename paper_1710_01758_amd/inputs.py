@@ -59,6 +59,11 @@ class SliceSpec:
 
 # Five workloads: small single slice, the headline 256^2 x 12 slice, a large
 # 512^2 x 32 slice, a ragged 64-slice batch and the learned-correction case.
+# Regularisation parameter sets (mu, lambda, gamma) of the paper's Methods
+# section, used for the per-Bregman-iteration comparison of preconditioners.
+PARAM_SETS = {1: (1e-3, 4e-3, 1e-3), 2: (1e-2, 4e-3, 1e-3), 3: (1e-3, 4e-3, 4e-3)}
+
+
 CFG1 = SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1)
 CFG2 = SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3)
 CFG3 = SliceSpec(512, 512, 32, 6.0, 32, vd=True, wavelet="db4", levels=4)

@@ -455,3 +455,33 @@ def test_concurrent_size_groups_equal_serial(torch, B):
         ctx.close()
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+def test_parameter_sets_iteration_counts_match_oracle(torch, B):
+    """Per-Bregman-iteration PCG counts for the paper's three parameter sets
+    and none / Jacobi / circulant (64 x 64 x 4, shrinks active): the GPU's
+    free-running counts follow the oracle's (total within 10% + 2, each solve
+    within 2), Jacobi matches none, and the circulant gain is smallest for
+    set 2."""
+    _say("parameter sets: counts vs oracle")
+    gains = {}
+    for sid, (mu, lam, gam) in gen.PARAM_SETS.items():
+        spec = gen.SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1, mu=mu, lam=lam, gam=gam, data_scale=1e3)
+        inst = _inst(spec, gen.eval_seed(1))
+        ctx, ksp = _ctx(B, [inst])
+        got = {}
+        for kind in ("none", "jacobi", "circulant"):
+            ref = osb.split_bregman(inst.kspace, inst.sens, inst.mask, mu, lam, gam, wavelet="haar", levels=1,
+                                    n_outer=20, precond=kind).pcg_iters
+            ctx.build_preconditioner(kind)
+            x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+            it, _ = ctx.split_bregman_recon(ksp, x, n_outer=20, tol=1e-3, maxit=1000)
+            g = it[:, 0].tolist()
+            _say(f"  set {sid} {kind}: gpu {sum(g)} oracle {sum(ref)}")
+            assert abs(sum(g) - sum(ref)) <= 0.1 * sum(ref) + 2, (sid, kind, g, ref)
+            assert max(abs(a - b) for a, b in zip(g, ref)) <= 2, (sid, kind, g, ref)
+            got[kind] = g
+        assert abs(sum(got["jacobi"]) - sum(got["none"])) <= 2
+        gains[sid] = sum(got["none"]) / sum(got["circulant"])
+        ctx.close()
+    assert gains[2] < gains[1] and gains[2] < gains[3], gains

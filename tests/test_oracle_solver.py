@@ -140,3 +140,23 @@ def test_sb_cfg1_scaled_reduces_error_and_iterations():
     assert sum(c.pcg_iters) < sum(u.pcg_iters)
     err_sos = H.rel_err(sb.sos_init(inst.kspace), inst.x_true)
     assert H.rel_err(c.x, inst.x_true) < err_sos
+
+
+def test_parameter_sets_reproduce_the_papers_iteration_structure():
+    """Results section, Fig. 5: per Bregman iteration the Jacobi preconditioner
+    does not change the PCG counts (diag(A) is constant when sum_c |S_c|^2 = 1,
+    so Jacobi-PCG is CG on a scaled system), the circulant preconditioner
+    needs several times fewer iterations, and the gain is smallest for set 2
+    (larger mu) while set 3 behaves like set 1.  64 x 64, 4 coils, shrinks
+    active (data scale 1e3)."""
+    gains = {}
+    for sid, (mu, lam, gam) in gen.PARAM_SETS.items():
+        spec = gen.SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1, mu=mu, lam=lam, gam=gam, data_scale=1e3)
+        inst = gen.make_instance(spec, gen.eval_seed(1))
+        it = {k: sb.split_bregman(inst.kspace, inst.sens, inst.mask, mu, lam, gam, wavelet="haar", levels=1,
+                                   n_outer=20, precond=k).pcg_iters for k in ("none", "jacobi", "circulant")}
+        assert it["jacobi"] == it["none"], sid
+        assert it["circulant"][0] * 2 <= it["none"][0], sid
+        gains[sid] = sum(it["none"]) / sum(it["circulant"])
+    assert min(gains.values()) > 2.0, gains
+    assert gains[2] < gains[1] and gains[2] < gains[3], gains
