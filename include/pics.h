@@ -21,7 +21,8 @@
  *   - a context holds a batch of nslices independent slices; image-shaped
  *     buffers pack the slices one after another (slice s starts at element
  *     sum_{s'<s} m_s' n_s'), coil-shaped buffers pack [nc_s][m_s][n_s] per
- *     slice, masks pack uint8[m_s] (line masks) per slice.
+ *     slice, masks pack uint8[m_s] (line masks) or uint8[m_s][n_s] (2D
+ *     masks) per slice.
  *     pics_sizes() returns the packed totals.
  *   - every data pointer is a device pointer owned by the caller; sizes are
  *     element counts.  The context borrows `sens` and `masks` until
@@ -57,7 +58,7 @@ extern "C" {
 #define PICS_ERR_STATE (-7)      /* call needs a preconditioner that was not built */
 
 #define PICS_MASK_LINES 0        /* uint8[m]: k-space row u sampled (all of axis 1) */
-#define PICS_MASK_2D 1           /* uint8[m][n] (not available in this build) */
+#define PICS_MASK_2D 1           /* uint8[m][n]: any sampling pattern (Methods, Undersampling, second scheme) */
 
 #define PICS_WAVELET_NONE 0
 #define PICS_WAVELET_HAAR 1
@@ -116,7 +117,11 @@ int build_preconditioner(pics_ctx* ctx, int32_t kind, const float* correction, f
 
 /* y = A x for every slice (Eq. system); terms selects PICS_TERM_* parts
  * (PICS_TERM_WAVELET_EXPLICIT routes the gamma term through W and W^H).
- * x and y image-packed c64, must not alias. */
+ * x and y image-packed c64, must not alias.  Line masks use one fused
+ * kernel (the data term factors into axis-0 transforms); 2D masks use
+ * row / column / row passes of full 2D transforms through the context's
+ * coil-shaped workspace.  With 2D masks k_c is the 2D cross-correlation,
+ * computed with FP32 FFTs. */
 int apply_A(pics_ctx* ctx, const void* x, void* y, int32_t terms);
 
 /* z = M^{-1} r = F^H diag(k)^{-1} F r (Eq. precon); needs a CIRCULANT or

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <sys/stat.h>
 #include <string>
 #include <vector>
@@ -25,7 +26,7 @@ struct pics_ctx {
   std::vector<SliceDev> sl;
   long long img_total = 0, coil_total = 0, mask_total = 0, aux_total = 0, max_pixels = 0;
   int max_levels = 0;
-  bool any_wavelet = false, any_nowavelet = false;
+  bool any_wavelet = false, any_nowavelet = false, any_2d = false;
   std::vector<int> wave_tiles;  // per level: max over slices of 16 x 16 coefficient tiles
 
   struct Group {
@@ -35,6 +36,7 @@ struct pics_ctx {
     int coil_groups = 1;  // workgroups sharing one tile's coil loop (autotuned)
     int nc_max = 0;
     int sidx = 0;         // index of the group's side stream
+    int mask_kind = 0;    // PICS_MASK_LINES or PICS_MASK_2D (slices of one group share it)
   };
   std::vector<Group> groups;
   int* all_idx_dev = nullptr;
@@ -183,6 +185,17 @@ Ws ws_for(const pics_ctx* c, const pics_ctx::Group& g) {
   return w;
 }
 
+// The system operator on one size group: the fused column-tile kernel for
+// line masks, the three-pass 2D-transform path for 2D masks.
+hipError_t launch_operator(pics_ctx* c, const pics_ctx::Group& g, int mode, int terms, int pk, double tol,
+                           const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out) {
+  if (g.mask_kind == PICS_MASK_2D)
+    return launch_apply2d(make_launch(c, g), ws_for(c, g), mode, terms, pk, tol, xin, zsrc, pold, pn, out,
+                          c->coiltmp);
+  return launch_col_apply(make_launch(c, g), ws_for(c, g), mode, terms, pk, tol, xin, zsrc, pold, pn, out,
+                          g.coil_groups, c->dpart, c->img_total);
+}
+
 bool levels_ok(int m, int n, int levels) {
   for (int l = 0; l < levels; ++l) {
     if ((m >> l) % 2 || (n >> l) % 2 || (m >> l) < 2 || (n >> l) < 2) return false;
@@ -320,7 +333,6 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
     if (!finite_nonneg(d.mu) || !finite_nonneg(d.lambda) || !finite_nonneg(d.gamma)) return PICS_ERR_INVALID;
     if (d.wavelet < 0 || d.wavelet > 2 || d.levels < 0 || d.levels > 12) return PICS_ERR_INVALID;
     if (d.mask_kind != PICS_MASK_LINES && d.mask_kind != PICS_MASK_2D) return PICS_ERR_INVALID;
-    if (d.mask_kind == PICS_MASK_2D) return PICS_ERR_UNSUPPORTED;
     if (!fft_size_supported(d.m) || !fft_size_supported(d.n)) return PICS_ERR_UNSUPPORTED;
     if (d.wavelet != PICS_WAVELET_NONE && !levels_ok(d.m, d.n, d.levels)) return PICS_ERR_UNSUPPORTED;
   }
@@ -332,7 +344,7 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   c->desc.assign(descs, descs + nslices);
   hipGetDevice(&c->device);
 
-  std::map<std::pair<int, int>, int> gidx;
+  std::map<std::tuple<int, int, int>, int> gidx;
   for (int s = 0; s < nslices; ++s) {
     const pics_desc& d = descs[s];
     SliceDev sd{};
@@ -356,15 +368,17 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
     c->aux_total += (long long)(d.n / kColT) * d.m;
     c->max_pixels = std::max(c->max_pixels, N);
     c->max_levels = std::max(c->max_levels, sd.levels);
+    if (d.mask_kind == PICS_MASK_2D) c->any_2d = true;
     if (sd.levels > 0) c->any_wavelet = true;
     else c->any_nowavelet = true;
     c->sl.push_back(sd);
-    auto key = std::make_pair(d.m, d.n);
+    auto key = std::make_tuple(d.m, d.n, (int)d.mask_kind);
     auto it = gidx.find(key);
     if (it == gidx.end()) {
       gidx[key] = (int)c->groups.size();
       c->groups.push_back({d.m, d.n, {s}, nullptr});
       c->groups.back().nc_max = d.ncoils;
+      c->groups.back().mask_kind = d.mask_kind;
     } else {
       c->groups[it->second].idx.push_back(s);
       c->groups[it->second].nc_max = std::max(c->groups[it->second].nc_max, (int)d.ncoils);
@@ -490,11 +504,47 @@ int build_preconditioner(pics_ctx* c, int32_t kind, const float* correction, flo
   for (int attempt = 0; attempt < 2; ++attempt) {
     const float* corr = (kind == PICS_PRECOND_LEARNED && attempt == 0) ? correction : nullptr;
     {
+      // line masks: axis-0 transforms of the coil maps give Pbar (and the
+      // pixel coil energy in jac); 2D masks: full 2D transforms give P
       GroupFork fk(c);
-      for (auto& g : c->groups) HIPCHK(c, launch_col_coil_power(make_launch(c, g), ws_for(c, g), c->pbar, c->jac));
+      for (auto& g : c->groups) {
+        if (g.mask_kind == PICS_MASK_2D) {
+          HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 2, c->sens, c->coiltmp));
+          HIPCHK(c, launch_col_power2d(make_launch(c, g), ws_for(c, g), c->coiltmp, c->ftmp, c->jac));
+        } else {
+          HIPCHK(c, launch_col_coil_power(make_launch(c, g), ws_for(c, g), c->pbar, c->jac));
+        }
+      }
       HIPCHK(c, fk.join());
     }
     HIPCHK(c, hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
+    if (c->any_2d) {
+      // 2D masks: k_c = IDFT(DFT(r) conj(DFT(P))) / N^3 (t, z, r, p as scratch)
+      const Simple S = make_simple(c);
+      HIPCHK(c, launch_corr_prep(S, w, c->ftmp, c->t, c->z));
+      {
+        GroupFork fk(c);
+        for (auto& g : c->groups) {
+          if (g.mask_kind != PICS_MASK_2D) continue;
+          HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 0, c->t, c->r));
+          HIPCHK(c, launch_col_fft(make_launch(c, g), ws_for(c, g), 0, c->r, c->t));
+          HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 0, c->z, c->p));
+          HIPCHK(c, launch_col_fft(make_launch(c, g), ws_for(c, g), 0, c->p, c->z));
+        }
+        HIPCHK(c, fk.join());
+      }
+      HIPCHK(c, launch_corr_mul(S, w, c->t, c->z));
+      {
+        GroupFork fk(c);
+        for (auto& g : c->groups) {
+          if (g.mask_kind != PICS_MASK_2D) continue;
+          HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 0, c->t, c->r));
+          HIPCHK(c, launch_col_fft(make_launch(c, g), ws_for(c, g), 1, c->r, c->t));
+        }
+        HIPCHK(c, fk.join());
+      }
+      HIPCHK(c, launch_build_k2d(S, w, c->t, corr, c->jac, c->kraw, c->kinv, c->jac, c->bad));
+    }
     HIPCHK(c, launch_build_k(make_simple(c), w, c->pbar, corr, c->kraw, c->kinv, c->jac, c->bad));
     HIPCHK(c, hipMemcpyAsync(c->flag_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -522,9 +572,8 @@ int apply_A(pics_ctx* c, const void* x, void* y, int32_t terms) {
   {
     GroupFork fk(c);
     for (auto& g : c->groups)
-      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, kterms, c->pk, 0.0, (const float2*)x,
-                                 nullptr, nullptr, nullptr, (float2*)y, g.coil_groups, c->dpart,
-                                 c->img_total));
+      HIPCHK(c, launch_operator(c, g, CA_APPLY, kterms, c->pk, 0.0, (const float2*)x, nullptr, nullptr, nullptr,
+                                (float2*)y));
     HIPCHK(c, fk.join());
   }
   if (explicit_w) {
@@ -605,8 +654,7 @@ int enq_pcg_setup(pics_ctx* c, const float2* b, float2* x, double tol, int maxit
     GroupFork fk(c);
     for (auto& g : c->groups) {
       if (!q_valid)
-        HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr,
-                                   nullptr, c->q, g.coil_groups, c->dpart, c->img_total));
+        HIPCHK(c, launch_operator(c, g, CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr, nullptr, c->q));
       HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
                                   c->t, maxit, maxit_dev));
     }
@@ -637,8 +685,7 @@ int enq_pcg_iters(pics_ctx* c, float2* x, double tol, int k0, int count) {
     for (int k = k0; k < k0 + count; ++k) {
       float2* pold = pbuf[k & 1];
       float2* pnew = pbuf[(k + 1) & 1];
-      HIPCHK(c, launch_col_apply(make_launch(c, g), ws_for(c, g), CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, pold,
-                                 pnew, c->q, g.coil_groups, c->dpart, c->img_total));
+      HIPCHK(c, launch_operator(c, g, CA_PCG, TERM_ALL, pk, tol, nullptr, zsrc, pold, pnew, c->q));
       HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, pnew,
                                   nullptr, c->t));
       if (circ) {
@@ -1268,6 +1315,7 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
   HIPCHK(c, hipEventCreate(&e1));
   HIPCHK(c, launch_fill(c->stream, c->p, c->img_total, make_float2(1.f, 0.5f)));
   for (auto& g : c->groups) {
+    if (g.mask_kind == PICS_MASK_2D) continue;  // the 2D path has no coil split
     const std::string key = group_key(g);
     auto hit = cache.find(key);
     if (hit != cache.end() && hit->second >= 1 && hit->second <= g.nc_max) {

@@ -140,6 +140,17 @@ hipError_t launch_col_sb_init(const Launch& L, const Ws& w, const float2* coil_r
 hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, float* energy);
 hipError_t launch_col_coil_energy(const Launch& L, const Ws& w, const float2* coil_rows, float* energy);
 
+// ---- 2D sampling masks (k_mask2d.hip)
+// the system operator as row / column / row passes through the coil buffer
+// `coil` (coil-shaped); modes and arguments as launch_col_apply
+hipError_t launch_apply2d(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol, const float2* xin,
+                          const float2* zsrc, const float2* pold, float2* pn, float2* out, float2* coil);
+hipError_t launch_col_power2d(const Launch& L, const Ws& w, const float2* coil_rows, float* P, float* energy);
+hipError_t launch_corr_prep(const Simple& S, const Ws& w, const float* P, float2* a, float2* b);
+hipError_t launch_corr_mul(const Simple& S, const Ws& w, float2* a, const float2* b);
+hipError_t launch_build_k2d(const Simple& S, const Ws& w, const float2* a, const float* corr, const float* energy,
+                            float* kraw, float* kinv, float* jac, int* bad);
+
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
 hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,

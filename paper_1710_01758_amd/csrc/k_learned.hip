@@ -47,15 +47,16 @@ __global__ __launch_bounds__(256) void k_features(Ws w, const float* __restrict_
     double pm = 0.0, pe = 0.0, pk = 0.0;
     for (int i = 0; i < fm; ++i) {
       const int u = (a * fm + i - m / 2 + m) % m;
-      pm += mk[u] ? 1.0 : 0.0;
+      if (sd.mask_kind == 0) pm += mk[u] ? fn : 0.0;
       for (int jj = 0; jj < fn; ++jj) {
         const int v = (b * fn + jj - n / 2 + n) % n;
         const long long p = sd.img + (long long)u * n + v;
+        if (sd.mask_kind != 0) pm += mk[(long long)u * n + v] ? 1.0 : 0.0;
         pe += energy[p];
         pk += kraw[p];
       }
     }
-    f[0 * CELLS + cell] = (float)(pm / fm);
+    f[0 * CELLS + cell] = (float)(pm / (fm * fn));
     f[1 * CELLS + cell] = (float)(pe / (fm * fn));
     f[2 * CELLS + cell] = (float)(pk / (fm * fn));
     se += pe / (fm * fn);

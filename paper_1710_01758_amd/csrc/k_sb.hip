@@ -519,6 +519,7 @@ __global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict_
   __shared__ int ssum;
   const int s = blockIdx.y;
   const SliceDev sd = w.sl[s];
+  if (sd.mask_kind != 0) return;  // 2D masks: k_build_k2d
   const int m = sd.m, n = sd.n;
   const int ntile = n / kColT;
   const uint8_t* mk = w.mask + sd.mask;

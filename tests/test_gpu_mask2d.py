@@ -1,0 +1,162 @@
+"""GPU parity of the fully random 2D sampling path (Methods, Undersampling,
+second scheme) against the FP64 oracle: the three-pass system operator, the
+2D cross-correlation spectrum, M^-1, PCG (iteration-locked and free-running,
+none / Jacobi / circulant), Split Bregman, and batches mixing line and 2D
+masks of the same size.  Tolerances as for line masks: operator, k, M^-1
+1e-5; PCG iteration-locked 1e-4; Split Bregman iteration-locked 1e-3."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import pcg as opcg
+from oracle import precond as opre
+from oracle import sb as osb
+from oracle import wavelet as owav
+from paper_1710_01758_amd import inputs as gen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a ROCm device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1710_01758_amd import binding
+    binding.lib()
+    return binding
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+SPEC_SMALL = gen.SliceSpec(64, 64, 4, 4.0, 12, mask_kind="2d", wavelet="haar", levels=1)
+SPEC_256 = gen.SliceSpec(256, 256, 12, 4.0, 24, mask_kind="2d", wavelet="db4", levels=3)
+SPEC_RECT = gen.SliceSpec(256, 224, 8, 6.0, 16, mask_kind="2d", wavelet="db4", levels=2)
+
+
+def _insts():
+    return [gen.make_instance(SPEC_SMALL, gen.eval_seed(21)), gen.make_instance(SPEC_256, gen.eval_seed(22)),
+            gen.make_instance(SPEC_RECT, gen.eval_seed(23))]
+
+
+def test_2d_operator_matches_oracle(torch, B):
+    _say("2d mask: apply_A")
+    insts = _insts()
+    assert all(it.mask.ndim == 2 for it in insts)
+    ctx, _ = B.context_for(insts)
+    xs = [gen.random_image(900 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
+    xd = B.to_device(B.pack_images(xs))
+    yd = torch.empty_like(xd)
+    for terms in (B.TERM_ALL, B.TERM_DATA, B.TERM_TV | B.TERM_GAMMA, B.TERM_ALL | B.TERM_WAVELET_EXPLICIT):
+        ctx.apply_A(xd, yd, terms)
+        got = B.unpack_images(_host(yd), [(it.spec.m, it.spec.n) for it in insts])
+        for it, x, g in zip(insts, xs, got):
+            s = it.spec
+            mu = s.mu if terms & B.TERM_DATA else 0.0
+            lam = s.lam if terms & B.TERM_TV else 0.0
+            gam = s.gam if terms & B.TERM_GAMMA else 0.0
+            wave = owav.make(s.wavelet, s.levels) if terms & B.TERM_WAVELET_EXPLICIT else None
+            ref = ops.apply_A(x, it.sens, it.mask2d.astype(np.float64), mu, lam, gam, wave)
+            assert H.rel_err(g, ref) < 1e-5, (s.m, s.n, terms, H.rel_err(g, ref))
+
+
+def test_2d_spectrum_and_minv_match_oracle(torch, B):
+    _say("2d mask: k and M^-1")
+    insts = _insts()
+    ctx, _ = B.context_for(insts)
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    got = B.unpack_images(_host(khat), [(it.spec.m, it.spec.n) for it in insts])
+    rs = [gen.random_image(950 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
+    rd = B.to_device(B.pack_images(rs))
+    zd = torch.empty_like(rd)
+    ctx.apply_Minv(rd, zd)
+    zg = B.unpack_images(_host(zd), [(it.spec.m, it.spec.n) for it in insts])
+    for it, g, r, z in zip(insts, got, rs, zg):
+        s = it.spec
+        ref = opre.circulant_k(it.sens, it.mask2d.astype(np.float64), s.mu, s.lam, s.gam)
+        err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+        _say(f"  {s.m}x{s.n}: k max rel err {err:.2e}")
+        assert err < 1e-5, (s.m, s.n, err)
+        assert H.rel_err(z, opre.apply_minv(r, ref)) < 1e-5
+
+
+@pytest.mark.parametrize("precond", ["circulant", "none", "jacobi"])
+def test_2d_pcg_locked_and_free_running(torch, B, precond):
+    _say(f"2d mask: pcg {precond}")
+    it = gen.make_instance(SPEC_256, gen.eval_seed(22))
+    s = it.spec
+    r2d = it.mask2d.astype(np.float64)
+    A = lambda v: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
+    b = s.mu * ops.adjoint(it.kspace, it.sens, r2d)
+    ref = opcg.pcg(A, b, np.zeros_like(b), osb.make_minv(precond, it.sens, r2d, s.mu, s.lam, s.gam), 1e-3, 1000)
+    ctx, _ = B.context_for([it])
+    ctx.build_preconditioner(precond)
+    bd = B.to_device(b.astype(np.complex64).ravel())
+    xd = torch.zeros_like(bd)
+    iters, _, _, _ = ctx.pcg_solve(bd, xd, 0.0, 0, maxit_per_slice=[ref.iters])
+    assert iters[0] == ref.iters
+    assert H.rel_err(_host(xd).reshape(s.m, s.n), ref.x) < 1e-4
+    xd.zero_()
+    iters, _, status, _ = ctx.pcg_solve(bd, xd, 1e-3, 1000)
+    assert status[0] == 1 and abs(int(iters[0]) - ref.iters) <= 1, (iters[0], ref.iters)
+    xg = _host(xd).reshape(s.m, s.n).astype(np.complex128)
+    assert np.linalg.norm(b - A(xg)) / np.linalg.norm(b) <= 1.05e-3
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e3])
+def test_2d_split_bregman_locked(torch, B, scale):
+    _say(f"2d mask: split bregman, scale {scale}")
+    spec = gen.SliceSpec(64, 64, 4, 4.0, 12, mask_kind="2d", wavelet="haar", levels=1, data_scale=scale)
+    it = gen.make_instance(spec, gen.eval_seed(24))
+    ref = osb.split_bregman(it.kspace, it.sens, it.mask, spec.mu, spec.lam, spec.gam, wavelet="haar", levels=1,
+                            n_outer=8, precond="circulant")
+    ctx, ksp = B.context_for([it])
+    ctx.build_preconditioner("circulant")
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    iters, _ = ctx.split_bregman_recon(ksp, x, n_outer=8, tol=1e-3, maxit=1000, lock=ref.pcg_iters)
+    err = H.rel_err(_host(x).reshape(spec.m, spec.n), ref.x)
+    _say(f"  locked rel err {err:.2e}")
+    assert err < 1e-3
+    x.zero_()
+    it_free, _ = ctx.split_bregman_recon(ksp, x, n_outer=8, tol=1e-3, maxit=1000)
+    assert max(abs(int(a) - int(b)) for a, b in zip(it_free[:, 0], ref.pcg_iters)) <= 1
+
+
+def test_mixed_line_and_2d_batch_equals_per_slice(torch, B):
+    """Line and 2D masks of the same size form separate groups in one batch;
+    each slice's PCG result is bitwise that of a context holding it alone."""
+    _say("2d mask: mixed batch")
+    line = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3)
+    insts = [gen.make_instance(SPEC_256, gen.eval_seed(22)), gen.make_instance(line, gen.eval_seed(25)),
+             gen.make_instance(SPEC_SMALL, gen.eval_seed(21))]
+    bs = [it.spec.mu * ops.adjoint(it.kspace, it.sens, it.mask2d.astype(np.float64)) for it in insts]
+    ctx, _ = B.context_for(insts)
+    ctx.build_preconditioner("circulant")
+    bd = B.to_device(B.pack_images(bs))
+    xd = torch.zeros_like(bd)
+    it_b, _, _, _ = ctx.pcg_solve(bd, xd, 1e-3, 100)
+    xb = _host(xd)
+    offs = np.cumsum([0] + [it.spec.m * it.spec.n for it in insts])
+    for i, it in enumerate(insts):
+        c1, _ = B.context_for([it])
+        c1.build_preconditioner("circulant")
+        b1 = B.to_device(bs[i].astype(np.complex64).ravel())
+        x1 = torch.zeros_like(b1)
+        it1, _, _, _ = c1.pcg_solve(b1, x1, 1e-3, 100)
+        assert it1[0] == it_b[i]
+        assert np.array_equal(_host(x1), xb[offs[i]:offs[i + 1]])
