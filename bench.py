@@ -153,6 +153,48 @@ def workload_section(torch, B, insts, label, steps=2):
                                "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": byts}}
 
 
+def mask2d_section(torch, B, batch=32, steps=2):
+    """The fully random variable-density 2D mask at 256 x 256 x 12 (R = 4,
+    24 x 24 centre): reconstructions per second of a batch, PCG iterations of
+    the first solve and over 20 Bregman iterations (none / circulant), and the
+    apply_A rate against the algorithmic floor 8 N (N_c + 2) and against the
+    three-pass traffic 8 N (5 N_c + 3) of the 2D-transform path."""
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, mask_kind="2d", wavelet="db4", levels=3)
+    insts = [gen.make_instance(spec, gen.eval_seed(6, i)) for i in range(batch)]
+    ctx, ksp = B.context_for(insts)
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+
+    def run(kind="circulant"):
+        ctx.build_preconditioner(kind)
+        return ctx.split_bregman_recon(ksp, x, n_outer=20, tol=1e-3, maxit=1000)[0]
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        it = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    it_none = run("none")
+    run()
+    xa = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    ya = torch.empty_like(xa)
+    t_apply = time_apply_kernel(torch, ctx, xa, ya, reps=20)
+    n_pix = spec.m * spec.n * batch
+    floor = 8 * n_pix * (spec.ncoils + 2)
+    passes = 8 * n_pix * (5 * spec.ncoils + 3)
+    ctx.close()
+    return {"workload": "256x256, 12 coils, random variable-density 2D mask R=4 (24x24 centre), TV + db4 x3, "
+                        f"batch of {batch}",
+            "recons_per_s": round(batch / dt, 2), "ms_per_batch": round(dt * 1e3, 3),
+            "pcg_iters": {"none": {"first_solve": int(it_none[0, 0]), "total_20_solves": int(it_none[:, 0].sum())},
+                          "circulant": {"first_solve": int(it[0, 0]), "total_20_solves": int(it[:, 0].sum())}},
+            "apply_A": {"avg_us": round(t_apply * 1e6, 2), "bytes_floor": floor, "bytes_three_pass": passes,
+                        "GBs_vs_floor": round(floor / t_apply / 1e9, 1),
+                        "GBs_three_pass": round(passes / t_apply / 1e9, 1),
+                        "frac_three_pass": round(passes / t_apply / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
 def param_sets_section(torch, B, nslices=8):
     """PCG iterations per Bregman iteration for the paper's three parameter
     sets with none / Jacobi / circulant at 256 x 256 x 12 (the structure of the
@@ -235,7 +277,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip training / evaluating the learned correction")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 512^2 x 32 slice, the ragged batch and the parameter-set comparison")
+                    help="skip the 512^2 x 32 slice, the ragged batch, the 2D-mask batch and the "
+                         "parameter-set comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--mode", choices=["full", "apply"], default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs)")
@@ -347,6 +390,8 @@ def main():
             torch, B, [gen.make_instance(sp, gen.eval_seed(4, i)) for i, sp in enumerate(specs)],
             "64 slices {128^2, 192^2, 256x224, 320^2}, 8-32 coils, R in {3,4,6}, TV + db4 x3")
     if not a.no_extra:
+        log("bench: 2D random variable-density mask, batch of 32")
+        out["mask2d_256x256x12"] = mask2d_section(torch, B)
         log("bench: parameter sets 1-3, none / Jacobi / circulant")
         out["param_sets_256x256x12"] = param_sets_section(torch, B)
     if not a.no_learned:
