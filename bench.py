@@ -195,6 +195,55 @@ def mask2d_section(torch, B, batch=32, steps=2):
                         "frac_three_pass": round(passes / t_apply / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
+def coil_compression_section(torch, B, batch=32, nvirt=6, steps=2):
+    """Coil compression (the paper's Fig. 7 comparison) at 256 x 256 x 12:
+    Split Bregman with all 12 coils and with the 6 most dominant virtual coils
+    (circulant preconditioner rebuilt on them): reconstructions per second of
+    a batch of 32 (compression included in the compressed timing), slice 0's
+    PCG iterations per Bregman iteration and the retained coil energy; at the
+    literal data scale and at 1e3."""
+    out = {}
+    for scale in (1.0, 1e3):
+        spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=scale)
+        insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(batch)]
+        ctx, ksp = B.context_for(insts)
+        tot = nvirt * spec.m * spec.n * batch
+        kout = torch.empty(tot, dtype=torch.complex64, device="cuda")
+        sout = torch.empty(tot, dtype=torch.complex64, device="cuda")
+        descs = [dict(B.spec_desc(spec), ncoils=nvirt) for _ in insts]
+        masks = B.to_device(B.pack_masks([it.mask for it in insts]))
+        eig = ctx.coil_compress(ksp, nvirt, kout, sout)
+        cv = B.Context(descs, sout, masks)
+        x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+
+        def full():
+            ctx.build_preconditioner("circulant")
+            return ctx.split_bregman_recon(ksp, x, n_outer=20, tol=1e-3, maxit=1000)[0]
+
+        def compressed():
+            ctx.coil_compress(ksp, nvirt, kout, sout)
+            cv.build_preconditioner("circulant")
+            return cv.split_bregman_recon(kout, x, n_outer=20, tol=1e-3, maxit=1000)[0]
+
+        row = {}
+        for name, fn in (("all_12_coils", full), (f"virtual_{nvirt}_coils", compressed)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                it = fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            row[name] = {"recons_per_s": round(batch / dt, 1), "slice0_per_bregman_iteration": it[:, 0].tolist(),
+                         "mean_total": float(it.sum(axis=0).mean())}
+        w = eig[:spec.ncoils]
+        row["retained_energy_slice0"] = round(float(w[:nvirt].sum() / w.sum()), 6)
+        out[f"data_scale_{scale:g}"] = row
+        ctx.close()
+        cv.close()
+    return out
+
+
 def param_sets_section(torch, B, nslices=8):
     """PCG iterations per Bregman iteration for the paper's three parameter
     sets with none / Jacobi / circulant at 256 x 256 x 12 (the structure of the
@@ -392,6 +441,8 @@ def main():
     if not a.no_extra:
         log("bench: 2D random variable-density mask, batch of 32")
         out["mask2d_256x256x12"] = mask2d_section(torch, B)
+        log("bench: coil compression 12 -> 6 virtual coils")
+        out["coil_compression_256x256x12"] = coil_compression_section(torch, B)
         log("bench: parameter sets 1-3, none / Jacobi / circulant")
         out["param_sets_256x256x12"] = param_sets_section(torch, B)
     if not a.no_learned:

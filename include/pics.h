@@ -162,6 +162,22 @@ int pcg_solve(pics_ctx* ctx, const void* b, void* x, double tol, int32_t maxit, 
 int split_bregman_recon(pics_ctx* ctx, const void* kspace, int32_t n_outer, int32_t n_inner, double tol,
                         int32_t maxit, const int32_t* lock_iters, void* x_out, int32_t* pcg_iters);
 
+/* Coil compression (Methods, Coil compression): per slice the covariance
+ * C = sum over k-space samples of y y^H of the slice's coil data, its
+ * eigenvectors U by descending eigenvalue (cyclic Jacobi in FP64 on the GPU),
+ * and the nvirt most dominant virtual coils y_v = U_v^H y and S_v = U_v^H S
+ * of the data and of the context's coil maps.  kspace: coil-packed c64 as
+ * for split_bregman_recon; kspace_out, sens_out: caller-owned, packed with
+ * nvirt coils per slice (nvirt m_s n_s c64 elements for slice s, slices in
+ * order) -- a new context over sens_out with ncoils = nvirt reconstructs the
+ * compressed problem.  eig_out (host, optional): the eigenvalues of every
+ * slice, descending, concatenated (ncoils_s per slice).  Uses the context's
+ * coil workspace; at most 32 coils per slice (PICS_ERR_UNSUPPORTED);
+ * 1 <= nvirt <= ncoils of every slice (PICS_ERR_INVALID).  Synchronises the
+ * stream when eig_out is given. */
+int pics_coil_compress(pics_ctx* ctx, const void* kspace, int32_t nvirt, void* kspace_out, void* sens_out,
+                       double* eig_out);
+
 /* Options.
  * PICS_OPT_POLL_CHUNK: PCG iterations enqueued between host convergence polls
  *   (first poll; later polls double it, up to 32).  Default 2.

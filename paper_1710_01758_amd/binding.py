@@ -63,6 +63,7 @@ def signatures():
         "split_bregman_recon": (ctypes.c_int, [vp, vp, i32, i32, dbl, i32, pi32, vp, pi32]),
         "pics_set_option": (ctypes.c_int, [vp, i32, i64]),
         "pics_autotune": (ctypes.c_int, [vp, i32]),
+        "pics_coil_compress": (ctypes.c_int, [vp, vp, i32, vp, vp, pdbl]),
         "pics_get_tuning": (ctypes.c_int, [vp, pi32, i32]),
         "pics_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pics_last_error": (ctypes.c_char_p, [vp]),
@@ -212,6 +213,14 @@ class Context:
                                         iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         self._check(rc)
         return iters, rc
+
+    def coil_compress(self, kspace, nvirt: int, kspace_out, sens_out):
+        """Compress every slice to its nvirt most dominant virtual coils;
+        returns the eigenvalues (descending, concatenated per slice)."""
+        eig = np.zeros(sum(int(d["ncoils"]) for d in self.descs), np.float64)
+        self._check(self.L.pics_coil_compress(self.h, _ptr(kspace), int(nvirt), _ptr(kspace_out), _ptr(sens_out),
+                                              eig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return eig
 
     def features(self, khat, out):
         """Feature planes [nslices][6][64][64] (float32 device tensor `out`)."""

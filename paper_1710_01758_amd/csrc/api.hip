@@ -966,6 +966,33 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
 
 }  // extern "C"
 
+extern "C" {
+
+int pics_coil_compress(pics_ctx* c, const void* kspace, int32_t nvirt, void* kspace_out, void* sens_out,
+                       double* eig_out) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!kspace || !kspace_out || !sens_out) return fail(c, PICS_ERR_INVALID, "coil_compress: null buffer");
+  for (const SliceDev& sd : c->sl) {
+    if (sd.nc > 32) return fail(c, PICS_ERR_UNSUPPORTED, "coil_compress: at most 32 coils per slice");
+    if (nvirt < 1 || nvirt > sd.nc) return fail(c, PICS_ERR_INVALID, "coil_compress: nvirt %d out of range", nvirt);
+  }
+  const Ws w = make_ws(c);
+  HIPCHK(c, launch_coil_compress(make_simple(c), w, (const float2*)kspace, c->sens, nvirt, (double2*)c->coiltmp,
+                                 (float2*)kspace_out, (float2*)sens_out));
+  if (eig_out) {
+    std::vector<double> slots((size_t)c->nslices * kSlots * kPartMax);
+    HIPCHK(c, hipMemcpyAsync(slots.data(), c->part, sizeof(double) * slots.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    long long o = 0;
+    for (int s = 0; s < c->nslices; ++s)
+      for (int k = 0; k < c->sl[s].nc; ++k) eig_out[o++] = slots[((size_t)s * kSlots + P_AUX) * kPartMax + k];
+  }
+  return PICS_OK;
+}
+
+}  // extern "C"
+
 // =================================================================== learned
 namespace {
 const int kLayerSpec[kNetLayers][3] = {{6, 32, 1}, {32, 32, 1}, {32, 32, 2}, {32, 32, 4}, {32, 32, 8}, {32, 16, 1}};

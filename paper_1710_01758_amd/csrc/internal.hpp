@@ -151,6 +151,11 @@ hipError_t launch_corr_mul(const Simple& S, const Ws& w, float2* a, const float2
 hipError_t launch_build_k2d(const Simple& S, const Ws& w, const float2* a, const float* corr, const float* energy,
                             float* kraw, float* kinv, float* jac, int* bad);
 
+// ---- coil compression (k_coils.hip); scratch: the coil workspace viewed as
+// double2, per slice at coil offset / 2; eigenvalues to the P_AUX slot
+hipError_t launch_coil_compress(const Simple& S, const Ws& w, const float2* ksp, const float2* sens, int nvirt,
+                                double2* scratch, float2* ksp_out, float2* sens_out);
+
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
 hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,
