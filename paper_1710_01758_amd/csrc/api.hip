@@ -365,7 +365,7 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
     c->img_total += N;
     c->coil_total += N * d.ncoils;
     c->mask_total += d.mask_kind == PICS_MASK_LINES ? d.m : N;
-    c->aux_total += (long long)(d.n / kColT) * d.m;
+    c->aux_total += (long long)(d.n / col_tile(d.m)) * d.m;
     c->max_pixels = std::max(c->max_pixels, N);
     c->max_levels = std::max(c->max_levels, sd.levels);
     if (d.mask_kind == PICS_MASK_2D) c->any_2d = true;

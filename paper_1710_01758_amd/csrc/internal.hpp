@@ -5,9 +5,10 @@
 
 namespace pics {
 
-constexpr int kColT = 16;     // columns per column tile
+constexpr int kColT = 16;     // columns per column tile (8 for columns of length 1024)
+__host__ __device__ constexpr int col_tile(int m) { return m >= 1024 ? 8 : kColT; }
 constexpr int kRowRR = 16;    // rows per row tile
-constexpr int kPartMax = 64;  // partial sums per slice per reduction
+constexpr int kPartMax = 128;  // partial sums per slice per reduction
 
 // reduction slots (per slice: kSlots x kPartMax doubles)
 enum PartSlot { P_SIGMA = 0, P_RR = 1, P_BB = 2, P_RHO0 = 3, P_RHO1 = 4, P_AUX = 5, kSlots = 6 };

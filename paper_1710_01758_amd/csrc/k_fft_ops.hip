@@ -32,7 +32,7 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
     Ws w, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
     const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, int ngroups,
     float2* __restrict__ dpart, long long dstride) {
-  constexpr int NT = ApplyCfg<M>::NT, E = ApplyCfg<M>::E, T = kColT, TH = ApplyCfg<M>::THREADS;
+  constexpr int NT = ApplyCfg<M>::NT, E = ApplyCfg<M>::E, T = ApplyCfg<M>::T, TH = ApplyCfg<M>::THREADS;
   constexpr int TS = T + 2;  // tile stride with the two halo columns
   constexpr int HP = (2 * M + TH - 1) / TH;
   constexpr bool DUAL = ApplyDual<M>::value;
@@ -152,11 +152,19 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
     const float inv_m = 1.0f / M;
     const float2* __restrict__ S = w.sens + sd.coil + t * n + col;
     const int plane = M * n;
+    // the next coil's maps are prefetched except at length 1024, where the
+    // extra registers would spill
+    constexpr bool PREFETCH = M < 1024;
     float2 sv[E], sn[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) sv[e] = S[(long long)c0 * plane + NT * e * n];
     for (int c = c0; c < sd.nc; c += cstep) {
-      if (c + cstep < sd.nc) {
+      if (!PREFETCH && c != c0) {
+        const float2* __restrict__ Sc = S + (long long)c * plane;
+#pragma unroll
+        for (int e = 0; e < E; ++e) sv[e] = Sc[NT * e * n];
+      }
+      if (PREFETCH && c + cstep < sd.nc) {
         const float2* __restrict__ Sn = S + (long long)(c + cstep) * plane;
 #pragma unroll
         for (int e = 0; e < E; ++e) sn[e] = Sn[NT * e * n];
@@ -179,8 +187,10 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
       }
 #pragma unroll
       for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(sv[e], v[e]));
+      if (PREFETCH) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) sv[e] = sn[e];
+        for (int e = 0; e < E; ++e) sv[e] = sn[e];
+      }
     }
   }
   if (PH == AP_PART) {
@@ -279,7 +289,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
     if (st->done) return;
     it = st->it_r;
     // sigma partials: one per column tile (line masks) or row tile (2D masks)
-    const int nrt = sd.m / kRowRR, nct = sd.mask_kind == 0 ? N / kColT : nrt;
+    const int nrt = sd.m / kRowRR, nct = sd.mask_kind == 0 ? N / col_tile(sd.m) : nrt;
     const double sigma = part_sum(part_ptr(w.part, s, P_SIGMA), nct);
     const double rho = part_sum(part_ptr(w.part, s, P_RHO0 + (it & 1)), nrt);
     const double a = rho / sigma;
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_precond(Ws w, int use_state, int check, double tol,
                                                                      float2* __restrict__ tbuf) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[M * T];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
 template <int M, int DIR>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_fft(Ws w, const float2* __restrict__ in,
                                                                 float2* __restrict__ out) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[M * T];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
@@ -478,7 +488,7 @@ template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const float2* __restrict__ coil_rows,
                                                                      float2* __restrict__ g1, float2* __restrict__ g,
                                                                      float2* __restrict__ x) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[M * T];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
@@ -530,7 +540,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, double* __restrict__ pbar,
                                                                         float* __restrict__ energy) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[M * T];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
@@ -577,7 +587,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, dou
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, const float2* __restrict__ coil_rows,
                                                                         float* __restrict__ energy) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[M * T];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
@@ -605,7 +615,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, co
 
 // ============================================================== launchers
 
-#define PICS_FFT_SIZES(X) X(64) X(128) X(192) X(224) X(256) X(320) X(512)
+#define PICS_FFT_SIZES(X) X(64) X(128) X(192) X(224) X(256) X(320) X(512) X(1024)
 
 template <int M, int PH>
 void launch_col_apply_phase(dim3 grid, const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
@@ -625,7 +635,7 @@ hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, i
                             int ngroups, float2* dpart, long long dstride) {
   const int split = (ngroups > 1 && (terms & TERM_DATA)) ? ngroups : 1;
   if (split > 1 && !dpart) return hipErrorInvalidValue;
-  const dim3 grid(L.n / kColT, L.count);
+  const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                            \
   case M:                                                                                                       \
@@ -668,7 +678,7 @@ hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, con
 }
 
 hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t) {
-  const dim3 grid(L.n / kColT, L.count);
+  const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                           \
   case M:                                                                                                      \
@@ -719,7 +729,7 @@ hipError_t launch_row_fft(const Launch& L, const Ws& w, int inverse, int ncoil_m
 }
 
 hipError_t launch_col_fft(const Launch& L, const Ws& w, int inverse, const float2* in, float2* out) {
-  const dim3 grid(L.n / kColT, L.count);
+  const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                          \
   case M:                                                                                                     \
@@ -738,7 +748,7 @@ hipError_t launch_col_fft(const Launch& L, const Ws& w, int inverse, const float
 
 hipError_t launch_col_sb_init(const Launch& L, const Ws& w, const float2* coil_rows, float2* g1, float2* g,
                               float2* x) {
-  const dim3 grid(L.n / kColT, L.count);
+  const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                             \
   case M:                                                                                                        \
@@ -753,7 +763,7 @@ hipError_t launch_col_sb_init(const Launch& L, const Ws& w, const float2* coil_r
 }
 
 hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, float* energy) {
-  const dim3 grid(L.n / kColT, L.count);
+  const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                           \
   case M:                                                                                                      \
@@ -768,7 +778,7 @@ hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, flo
 }
 
 hipError_t launch_col_coil_energy(const Launch& L, const Ws& w, const float2* coil_rows, float* energy) {
-  const dim3 grid(L.n / kColT, L.count);
+  const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                               \
   case M:                                                                                                          \

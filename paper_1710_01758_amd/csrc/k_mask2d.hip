@@ -91,7 +91,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_sp(Ws w, int pk, dou
 // use_state: skip slices whose PCG solve has finished.
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_mask2d(Ws w, int use_state, float2* __restrict__ coil) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[M * T];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_acc(Ws w, int terms,
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_power2d(Ws w, const float2* __restrict__ coil_rows,
                                                                      float* __restrict__ P, float* __restrict__ energy) {
-  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = kColT;
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[M * T];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
@@ -303,13 +303,13 @@ __global__ __launch_bounds__(256) void k_build_k2d(Ws w, const float2* __restric
 
 // ============================================================== launchers
 
-#define PICS_2D_SIZES(X) X(64) X(128) X(192) X(224) X(256) X(320) X(512)
+#define PICS_2D_SIZES(X) X(64) X(128) X(192) X(224) X(256) X(320) X(512) X(1024)
 
 hipError_t launch_apply2d(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol, const float2* xin,
                           const float2* zsrc, const float2* pold, float2* pn, float2* out, float2* coil) {
   const bool data = (terms & TERM_DATA) != 0;
   if (mode == CA_PCG && !data) return hipErrorInvalidValue;  // the PCG mode always carries the data term
-  const dim3 rgrid(L.m / kRowRR, L.count), cgrid(L.n / kColT, L.count);
+  const dim3 rgrid(L.m / kRowRR, L.count), cgrid(L.n / col_tile(L.m), L.count);
   if (data) {
     switch (L.n) {
 #define PICS_CASE(N)                                                                                             \
@@ -361,7 +361,7 @@ hipError_t launch_apply2d(const Launch& L, const Ws& w, int mode, int terms, int
 }
 
 hipError_t launch_col_power2d(const Launch& L, const Ws& w, const float2* coil_rows, float* P, float* energy) {
-  const dim3 grid(L.n / kColT, L.count);
+  const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                         \
   case M:                                                                                                    \

@@ -521,7 +521,7 @@ __global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict_
   const SliceDev sd = w.sl[s];
   if (sd.mask_kind != 0) return;  // 2D masks: k_build_k2d
   const int m = sd.m, n = sd.n;
-  const int ntile = n / kColT;
+  const int ntile = n / col_tile(m);
   const uint8_t* mk = w.mask + sd.mask;
   if (threadIdx.x == 0) ssum = 0;
   __syncthreads();

@@ -15,7 +15,7 @@ template <int M, class P = Plan<M>>
 struct ColCfg {
   static constexpr int NT = P::NT;
   static constexpr int E = M / NT;
-  static constexpr int T = kColT;
+  static constexpr int T = col_tile(M);
   static constexpr int THREADS = NT * T;
 };
 
