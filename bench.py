@@ -433,6 +433,11 @@ def main():
         out["slice_512x512x32"] = workload_section(
             torch, B, [gen.make_instance(gen.CFG3, gen.eval_seed(3))],
             "512x512, 32 coils, variable-density lines R=6 (32 centre), TV + db4 x4")
+        log("bench: 1024x1024x12 slice")
+        out["slice_1024x1024x12"] = workload_section(
+            torch, B, [gen.make_instance(gen.SliceSpec(1024, 1024, 12, 4.0, 64, wavelet="db4", levels=4),
+                                         gen.eval_seed(7))],
+            "1024x1024, 12 coils, random lines R=4 (64 centre), TV + db4 x4 (the paper's largest size)")
         log("bench: ragged batch of 64 slices")
         specs = gen.cfg4_specs()
         out["ragged_batch_64"] = workload_section(
