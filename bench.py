@@ -360,15 +360,30 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
+    stream = torch.cuda.ExternalStream(ctx.stream) if ctx.stream else torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
     t0 = time.perf_counter()
     iters = None
+    evs[0].record(stream)
     for k in range(a.steps):
         iters = step()
+        evs[k + 1].record(stream)
         log(f"bench: step {k + 1}/{a.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(a.steps)])
     value = a.batch * a.steps / dt
     ms_per_step = dt / a.steps * 1e3
+
+    # the preconditioner build alone (Table 2 reports it separately)
+    for _ in range(2):
+        ctx.build_preconditioner("circulant")
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(5):
+        ctx.build_preconditioner("circulant")
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb) / 5 * 1e3
 
     # single-slice latency (one reconstruction alone)
     ctx1, ksp1 = B.context_for(insts[:1])
@@ -414,6 +429,9 @@ def main():
                                f"mu=1e-3 lambda=gamma=4e-3, 20 outer iters, PCG tol 1e-3, circulant; "
                                f"batch of {a.batch} slices per step, data_scale {a.scale:g}",
                    "global_batch": a.batch, "m": 256, "n": 256, "ncoils": 12, "parallelism": "none (1 GPU)"},
+        "step_ms_stats": {"median": round(float(np.median(step_ms)), 3), "p10": round(float(np.percentile(step_ms, 10)), 3),
+                          "p90": round(float(np.percentile(step_ms, 90)), 3), "source": "HIP events per step"},
+        "build_preconditioner_ms_batch": round(build_ms, 3),
         "single_slice_recons_per_s": round(single, 3),
         "coil_split": {"batch": split[0], "single_slice": split1[0]},
         "pcg_iters": {
