@@ -104,3 +104,45 @@ def test_status_strings_and_null_checks(lib):
     lib.pics_net_param_count.restype = ctypes.c_int64
     from oracle import learned as OL
     assert lib.pics_net_param_count() == OL.param_count()
+
+
+def _create(lib, descs, nslices=None):
+    """Call pics_create with host placeholder buffers: descriptor checks run
+    before any device call, so invalid descriptors are refused on any host."""
+    from paper_1710_01758_amd import binding as Bm
+    arr = (Bm.Desc * max(1, len(descs)))()
+    for i, d in enumerate(descs):
+        arr[i] = Bm.Desc(*d)
+    h = ctypes.c_void_p()
+    dummy = (ctypes.c_uint8 * 16)()
+    lib.pics_create.restype = ctypes.c_int
+    lib.pics_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(Bm.Desc),
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    n = len(descs) if nslices is None else nslices
+    return lib.pics_create(ctypes.byref(h), n, arr, ctypes.cast(dummy, ctypes.c_void_p),
+                           ctypes.cast(dummy, ctypes.c_void_p), None)
+
+
+GOOD = (256, 256, 12, 0, 2, 3, 1e-3, 4e-3, 4e-3)
+
+
+@pytest.mark.parametrize("desc,code", [
+    ((100, 256, 12, 0, 2, 3, 1e-3, 4e-3, 4e-3), "PICS_ERR_UNSUPPORTED"),   # no FFT plan for 100
+    ((256, 2048, 12, 0, 2, 3, 1e-3, 4e-3, 4e-3), "PICS_ERR_UNSUPPORTED"),  # beyond the largest plan
+    ((256, 256, 0, 0, 2, 3, 1e-3, 4e-3, 4e-3), "PICS_ERR_INVALID"),        # no coils
+    ((256, 256, 12, 7, 2, 3, 1e-3, 4e-3, 4e-3), "PICS_ERR_INVALID"),       # unknown mask kind
+    ((256, 256, 12, 0, 5, 3, 1e-3, 4e-3, 4e-3), "PICS_ERR_INVALID"),       # unknown wavelet
+    ((64, 64, 4, 0, 2, 7, 1e-3, 4e-3, 4e-3), "PICS_ERR_UNSUPPORTED"),      # 7 levels do not fit 64 x 64
+    ((256, 256, 12, 0, 2, 3, -1e-3, 4e-3, 4e-3), "PICS_ERR_INVALID"),      # negative mu
+    ((256, 256, 12, 0, 2, 3, 1e-3, float("nan"), 4e-3), "PICS_ERR_INVALID"),  # non-finite lambda
+])
+def test_create_refuses_invalid_descriptors(lib, desc, code):
+    d = _defines()
+    assert _create(lib, [GOOD, desc]) == d[code]
+
+
+def test_create_refuses_empty_batch_and_null_arguments(lib):
+    d = _defines()
+    assert _create(lib, [GOOD], nslices=0) == d["PICS_ERR_INVALID"]
+    lib.pics_create.restype = ctypes.c_int
+    assert lib.pics_create(None, 1, None, None, None, None) == d["PICS_ERR_INVALID"]

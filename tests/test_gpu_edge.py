@@ -1,0 +1,153 @@
+"""Degenerate and boundary cases of the GPU path: zero right-hand side,
+iteration cap, an empty sampling mask (with and without gamma), aliased or
+null buffers, an operator with no terms, zero Split Bregman iterations (the
+root-sum-of-squares start), the smallest slice with one coil, and a slice with
+many coils."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import pcg as opcg
+from oracle import precond as opre
+from oracle import sb as osb
+from paper_1710_01758_amd import inputs as gen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a ROCm device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1710_01758_amd import binding
+    binding.lib()
+    return binding
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def test_zero_rhs_gives_zero_solution_without_iterations(torch, B):
+    _say("edge: zero rhs")
+    it = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    ctx, _ = B.context_for([it])
+    ctx.build_preconditioner("circulant")
+    b = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    x = B.to_device(gen.random_image(5, 64, 64).astype(np.complex64).ravel())
+    iters, relres, status, rc = ctx.pcg_solve(b, x, 1e-3, 100)
+    assert iters[0] == 0 and status[0] == 1 and rc == B.PICS_OK
+    assert float(x.abs().max()) == 0.0
+
+
+def test_iteration_cap_is_a_warning(torch, B):
+    _say("edge: maxit")
+    it = gen.make_instance(gen.CFG2, gen.eval_seed(2))
+    s = it.spec
+    ctx, _ = B.context_for([it])
+    ctx.build_preconditioner("none")
+    b = s.mu * ops.adjoint(it.kspace, it.sens, it.mask2d.astype(np.float64))
+    bd = B.to_device(b.astype(np.complex64).ravel())
+    x = torch.zeros_like(bd)
+    iters, relres, status, rc = ctx.pcg_solve(bd, x, 1e-9, 3)
+    assert rc == B.PICS_WARN_MAXIT and status[0] == 0 and iters[0] == 3
+    assert relres[0] > 1e-9
+
+
+def _empty_mask_instance(gam):
+    spec = gen.SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1, gam=gam)
+    it = gen.make_instance(spec, gen.eval_seed(1, 3))
+    it.mask = np.zeros_like(it.mask)  # nothing sampled
+    it.kspace = np.zeros_like(it.kspace)
+    return it
+
+
+def test_empty_mask_without_gamma_is_not_positive(torch, B):
+    """No samples and gamma = 0: k vanishes at DC (Eq. Kdiag), so the circulant
+    preconditioner does not exist and the build says so."""
+    _say("edge: empty mask, gamma 0")
+    it = _empty_mask_instance(0.0)
+    ctx, _ = B.context_for([it])
+    with pytest.raises(B.PicsError) as e:
+        ctx.build_preconditioner("circulant")
+    assert e.value.code == -5  # PICS_ERR_NOT_POSITIVE
+
+
+def test_empty_mask_with_gamma_is_exactly_circulant(torch, B):
+    """No samples: A = lambda L + gamma I is circulant, M = A, and PCG needs one
+    iteration (against the oracle's solution)."""
+    _say("edge: empty mask, gamma > 0")
+    it = _empty_mask_instance(4e-3)
+    s = it.spec
+    ctx, _ = B.context_for([it])
+    ctx.build_preconditioner("circulant")
+    b = gen.random_image(6, 64, 64)
+    A = lambda v: ops.apply_A(v, it.sens, it.mask2d.astype(np.float64), s.mu, s.lam, s.gam)
+    ref = opcg.pcg(A, b, np.zeros_like(b), None, 1e-6, 1000)
+    bd = B.to_device(b.astype(np.complex64).ravel())
+    x = torch.zeros_like(bd)
+    iters, _, status, _ = ctx.pcg_solve(bd, x, 1e-6, 100)
+    assert iters[0] == 1 and status[0] == 1
+    assert H.rel_err(_host(x).reshape(64, 64), ref.x) < 1e-5
+
+
+def test_operator_without_terms_and_buffer_checks(torch, B):
+    _say("edge: no terms, aliasing")
+    it = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    ctx, _ = B.context_for([it])
+    x = B.to_device(gen.random_image(7, 64, 64).astype(np.complex64).ravel())
+    y = torch.full_like(x, 3.0)
+    ctx.apply_A(x, y, 0)
+    assert float(y.abs().max()) == 0.0
+    for call in (lambda: ctx.apply_Minv(x, x), lambda: ctx.pcg_solve(x, x, 1e-3, 10)):
+        with pytest.raises(B.PicsError) as e:
+            call()
+        assert e.value.code == -1  # PICS_ERR_INVALID
+    with pytest.raises(B.PicsError) as e:
+        ctx.apply_Minv(x, y)  # no circulant build yet
+    assert e.value.code == -7  # PICS_ERR_STATE
+
+
+def test_zero_outer_iterations_return_the_sum_of_squares_start(torch, B):
+    _say("edge: n_outer 0 and 1")
+    it = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    ctx, ksp = B.context_for([it])
+    ctx.build_preconditioner("circulant")
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    ctx.split_bregman_recon(ksp, x, n_outer=0)
+    assert H.rel_err(_host(x).reshape(64, 64), osb.sos_init(it.kspace)) < 1e-5
+    s = it.spec
+    ref = osb.split_bregman(it.kspace, it.sens, it.mask, s.mu, s.lam, s.gam, wavelet="haar", levels=1, n_outer=1)
+    iters, _ = ctx.split_bregman_recon(ksp, x, n_outer=1, lock=ref.pcg_iters)
+    assert H.rel_err(_host(x).reshape(64, 64), ref.x) < 1e-4
+
+
+@pytest.mark.parametrize("nc", [1, 48])
+def test_one_coil_and_many_coils(torch, B, nc):
+    _say(f"edge: {nc} coils")
+    spec = gen.SliceSpec(64, 64, nc, 3.0, 8, wavelet="haar", levels=1)
+    it = gen.make_instance(spec, gen.eval_seed(1, 10 + nc))
+    ctx, _ = B.context_for([it])
+    x = gen.random_image(8, 64, 64)
+    xd = B.to_device(x.astype(np.complex64).ravel())
+    yd = torch.empty_like(xd)
+    ctx.apply_A(xd, yd)
+    r2d = it.mask2d.astype(np.float64)
+    assert H.rel_err(_host(yd).reshape(64, 64), ops.apply_A(x, it.sens, r2d, spec.mu, spec.lam, spec.gam)) < 1e-5
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    k = opre.circulant_k(it.sens, r2d, spec.mu, spec.lam, spec.gam)
+    assert np.max(np.abs(_host(khat).reshape(64, 64) - k)) / k.max() < 1e-5
