@@ -309,3 +309,82 @@ def training_instances(count: int, base: int = TRAIN_SEED_BASE, m: int = 64, n: 
         spec = training_spec(rng, m, n, nc)
         out.append(make_instance(spec, base + i))
     return out
+
+
+# ------------------------------------------------------------------ volumes
+@dataclasses.dataclass
+class VolumeSpec:
+    """A 3D problem [p][m][n] (axis 0 = z): ncoils, a 2D random
+    variable-density pattern over the two phase-encode axes (z, y) with a
+    sampled centre, fully sampled along x, and the regularisation weights."""
+
+    p: int
+    m: int
+    n: int
+    ncoils: int
+    accel: float
+    centre: int
+    mu: float = 1e-3
+    lam: float = 4e-3
+    gam: float = 4e-3
+    noise_sigma: float = 1e-3
+    data_scale: float = 1.0
+
+
+@dataclasses.dataclass
+class VolumeInstance:
+    spec: VolumeSpec
+    seed: int
+    x_true: np.ndarray      # complex128 [p][m][n]
+    sens: np.ndarray        # complex128 [nc][p][m][n]
+    mask: np.ndarray        # uint8 [p][m][n]
+    kspace: np.ndarray      # complex128 [nc][p][m][n]
+
+
+def volume_phantom(p: int, m: int, n: int, rng: np.random.Generator, count: int = 8) -> np.ndarray:
+    """Sum of random complex ellipsoids on the voxel-centre grid of [-1, 1]^3."""
+    z = -1.0 + (2.0 * np.arange(p) + 1.0) / p
+    Y, X = _grid(m, n)
+    out = np.zeros((p, m, n), np.complex128)
+    for _ in range(count):
+        cz, cy, cx = rng.uniform(-0.5, 0.5, size=3)
+        az, ay, ax = rng.uniform(0.15, 0.5, size=3)
+        inten = rng.uniform(0.1, 1.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        inside = (((z[:, None, None] - cz) / az) ** 2 + ((Y[None] - cy) / ay) ** 2
+                  + ((X[None] - cx) / ax) ** 2) <= 1.0
+        out[inside] += inten * complex(math.cos(ph), math.sin(ph))
+    return out
+
+
+def volume_coil_maps(p: int, m: int, n: int, nc: int, rng: np.random.Generator) -> np.ndarray:
+    """Gaussian bumps on a ring around the z axis at alternating heights, with
+    linear phase, normalised to sum_c |S_c|^2 = 1 at every voxel."""
+    z = -1.0 + (2.0 * np.arange(p) + 1.0) / p
+    Y, X = _grid(m, n)
+    S = np.empty((nc, p, m, n), np.complex128)
+    for c in range(nc):
+        a = 2.0 * math.pi * c / nc + rng.uniform(-math.pi / (2 * nc), math.pi / (2 * nc))
+        zc = 0.5 if c % 2 else -0.5
+        width = rng.uniform(0.6, 0.9)
+        phi0 = rng.uniform(0.0, 2.0 * math.pi)
+        gz, gy, gx = rng.uniform(-math.pi / 2, math.pi / 2, size=3)
+        cy, cx = 1.2 * math.sin(a), 1.2 * math.cos(a)
+        d2 = (X[None] - cx) ** 2 + (Y[None] - cy) ** 2 + (z[:, None, None] - zc) ** 2
+        S[c] = np.exp(-d2 / (2.0 * width**2)) * np.exp(1j * (phi0 + gz * z[:, None, None] + gy * Y[None]
+                                                             + gx * X[None]))
+    S /= np.sqrt(np.sum(np.abs(S) ** 2, axis=0))[None]
+    return S
+
+
+def make_volume_instance(spec: VolumeSpec, seed: int) -> VolumeInstance:
+    rp, rc, rm, rn = _streams(seed)
+    x = volume_phantom(spec.p, spec.m, spec.n, rp) * spec.data_scale
+    S = volume_coil_maps(spec.p, spec.m, spec.n, spec.ncoils, rc)
+    pe = random_2d_mask(spec.p, spec.m, spec.accel, spec.centre, rm)  # over (z, y)
+    mask = np.repeat(pe[:, :, None], spec.n, axis=2)
+    sig = spec.noise_sigma * spec.data_scale / math.sqrt(2.0)
+    shape = (spec.ncoils, spec.p, spec.m, spec.n)
+    noise = rn.normal(0.0, sig, size=shape) + 1j * rn.normal(0.0, sig, size=shape)
+    full = np.fft.fftn(S * x[None], axes=(-3, -2, -1), norm="ortho") + noise
+    return VolumeInstance(spec, seed, x, S, mask, full * mask[None].astype(np.float64))
