@@ -244,6 +244,42 @@ def coil_compression_section(torch, B, batch=32, nvirt=6, steps=2):
     return out
 
 
+def volume_section(torch, B):
+    """The 3D extension on a 128 x 256 x 256 volume with 8 coils (2D random
+    variable-density pattern over (z, y), fully sampled along x, R = 4): PCG
+    from 0 to 1e-3 with none and with the 3D circulant preconditioner
+    (iterations, seconds), the preconditioner build and one operator
+    application."""
+    spec = gen.VolumeSpec(128, 256, 256, 8, 4.0, 24)
+    inst = gen.make_volume_instance(spec, gen.eval_seed(9))
+    vol, ksp = B.volume_for(inst)
+    b = torch.empty(vol.voxels, dtype=torch.complex64, device="cuda")
+    vol.rhs(ksp, b)
+    out = {"workload": "volume 128x256x256, 8 coils, random VD (z, y) pattern R=4, 24x24 centre, fully sampled x"}
+    for kind in ("none", "circulant"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vol.build_preconditioner(kind)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        x = torch.zeros_like(b)
+        t0 = time.perf_counter()
+        it, rel, _ = vol.pcg_solve(b, x, 1e-3, 500)
+        torch.cuda.synchronize()
+        out[kind] = {"pcg_iters": it, "relres": rel, "solve_s": round(time.perf_counter() - t0, 4),
+                     "build_s": round(tb, 4)}
+    y = torch.empty_like(b)
+    vol.apply_A(b, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        vol.apply_A(b, y)
+    torch.cuda.synchronize()
+    out["apply_A_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+    vol.close()
+    return out
+
+
 def param_sets_section(torch, B, nslices=8):
     """PCG iterations per Bregman iteration for the paper's three parameter
     sets with none / Jacobi / circulant at 256 x 256 x 12 (the structure of the
@@ -464,6 +500,8 @@ def main():
     if not a.no_extra:
         log("bench: 2D random variable-density mask, batch of 32")
         out["mask2d_256x256x12"] = mask2d_section(torch, B)
+        log("bench: 3D volume 128x256x256x8")
+        out["volume_128x256x256x8"] = volume_section(torch, B)
         log("bench: coil compression 12 -> 6 virtual coils")
         out["coil_compression_256x256x12"] = coil_compression_section(torch, B)
         log("bench: parameter sets 1-3, none / Jacobi / circulant")

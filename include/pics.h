@@ -279,6 +279,40 @@ int pics_get_tuning(const pics_ctx* ctx, int32_t* coil_groups, int32_t max_group
 const char* pics_status_string(int status);
 const char* pics_last_error(const pics_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * 3D extension (the paper's Discussion names it as the next step): one volume
+ * [p][m][n] (axis 0 = z), coil maps [nc][p][m][n], a binary mask [p][m][n],
+ *   A = mu sum_c S_c^H F^H R F S_c + lambda (D_z^H D_z + D_y^H D_y + D_x^H D_x)
+ *       + gamma I
+ * with the unitary 3D DFT F and periodic backward differences, and the 3D
+ * circulant preconditioner k = mu k_c + lambda k_d + gamma, k_c(j) = (1/N^2)
+ * sum_l r(l) P(l - j), P = sum_c |DFT(s_c)|^2, k_d = 6 - 2 cos(2 pi w/p)
+ * - 2 cos(2 pi u/m) - 2 cos(2 pi v/n) (Eqs. K, Kdiag, d, diagonalelements one
+ * dimension up).  p, m, n must each have an FFT plan.  Buffers are device
+ * c64 volumes owned by the caller; the context borrows sens and mask and owns
+ * a workspace of 2 nc + 5 complex volumes.  Return codes as above. */
+typedef struct {
+  int32_t p, m, n, ncoils;
+  double mu, lambda, gamma;
+} pics3d_desc;
+typedef struct pics3d_ctx pics3d_ctx;
+int pics3d_create(pics3d_ctx** ctx, const pics3d_desc* desc, const void* sens, const uint8_t* mask, void* stream);
+int pics3d_destroy(pics3d_ctx* ctx);
+/* kind: PICS_PRECOND_NONE or PICS_PRECOND_CIRCULANT; khat_out (optional,
+ * device float [p][m][n]) receives k.  Synchronises the stream. */
+int pics3d_build_preconditioner(pics3d_ctx* ctx, int32_t kind, float* khat_out);
+int pics3d_apply_A(pics3d_ctx* ctx, const void* x, void* y);
+/* b = mu sum_c S_c^H F^H R y_c (the data part of the right-hand side, Eq.
+ * system); kspace: [nc][p][m][n] c64 (samples outside the mask ignored). */
+int pics3d_rhs(pics3d_ctx* ctx, const void* kspace, void* b);
+int pics3d_apply_Minv(pics3d_ctx* ctx, const void* r, void* z);
+/* PCG from the x given (Saad, Alg. 9.1, as pcg_solve): stop when
+ * ||r|| <= tol ||b|| or after maxit products A p (PICS_WARN_MAXIT); tol = 0
+ * runs exactly maxit iterations.  iters, relres: host, optional. */
+int pics3d_pcg_solve(pics3d_ctx* ctx, const void* b, void* x, double tol, int32_t maxit, int32_t* iters,
+                     double* relres);
+const char* pics3d_last_error(const pics3d_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,6 +43,11 @@ class Desc(ctypes.Structure):
                 ("mu", ctypes.c_double), ("lam", ctypes.c_double), ("gam", ctypes.c_double)]
 
 
+class Desc3(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("ncoils", ctypes.c_int32),
+                ("mu", ctypes.c_double), ("lam", ctypes.c_double), ("gam", ctypes.c_double)]
+
+
 _LIB = None
 
 
@@ -79,6 +84,14 @@ def signatures():
         "pics_net_loss_grad": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, pdbl]),
         "pics_net_adam_step": (ctypes.c_int, [vp, ctypes.c_float]),
         "pics_net_correction": (ctypes.c_int, [vp, vp, vp, vp]),
+        "pics3d_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(Desc3), vp, vp, vp]),
+        "pics3d_destroy": (ctypes.c_int, [vp]),
+        "pics3d_build_preconditioner": (ctypes.c_int, [vp, i32, vp]),
+        "pics3d_apply_A": (ctypes.c_int, [vp, vp, vp]),
+        "pics3d_rhs": (ctypes.c_int, [vp, vp, vp]),
+        "pics3d_apply_Minv": (ctypes.c_int, [vp, vp, vp]),
+        "pics3d_pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, i32, pi32, pdbl]),
+        "pics3d_last_error": (ctypes.c_char_p, [vp]),
     }
 
 
@@ -329,3 +342,66 @@ def context_for(instances, device="cuda", stream=None):
     ctx = Context([spec_desc(inst.spec) for inst in instances], sens, masks, stream)
     ksp = to_device(pack_images([inst.kspace for inst in instances]), device)
     return ctx, ksp
+
+
+class Volume:
+    """A 3D problem on libpics (volume [p][m][n], one context per volume)."""
+
+    def __init__(self, spec, sens, mask, stream=None):
+        import torch
+        self.L = lib()
+        self.spec = spec
+        self._keep = (sens, mask)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        d = Desc3(spec.p, spec.m, spec.n, spec.ncoils, spec.mu, spec.lam, spec.gam)
+        h = ctypes.c_void_p()
+        rc = self.L.pics3d_create(ctypes.byref(h), ctypes.byref(d), _ptr(sens), _ptr(mask), ctypes.c_void_p(stream))
+        if rc != PICS_OK:
+            raise PicsError(rc, self.L.pics_status_string(rc).decode())
+        self.h = h
+        self.voxels = spec.p * spec.m * spec.n
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise PicsError(rc, self.L.pics3d_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pics3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_preconditioner(self, kind: str = "circulant", khat=None) -> int:
+        return self._check(self.L.pics3d_build_preconditioner(self.h, PRECOND[kind], _ptr(khat)))
+
+    def apply_A(self, x, y) -> int:
+        return self._check(self.L.pics3d_apply_A(self.h, _ptr(x), _ptr(y)))
+
+    def apply_Minv(self, r, z) -> int:
+        return self._check(self.L.pics3d_apply_Minv(self.h, _ptr(r), _ptr(z)))
+
+    def rhs(self, kspace, b) -> int:
+        return self._check(self.L.pics3d_rhs(self.h, _ptr(kspace), _ptr(b)))
+
+    def pcg_solve(self, b, x, tol: float, maxit: int):
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        rc = self._check(self.L.pics3d_pcg_solve(self.h, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(it),
+                                                 ctypes.byref(rel)))
+        return it.value, rel.value, rc
+
+
+def volume_for(inst, device="cuda", stream=None):
+    """A Volume context and its k-space (device c64) for an inputs.VolumeInstance."""
+    sens = to_device(np.asarray(inst.sens, np.complex64).ravel(), device)
+    mask = to_device(np.asarray(inst.mask, np.uint8).ravel(), device)
+    ksp = to_device(np.asarray(inst.kspace, np.complex64).ravel(), device)
+    return Volume(inst.spec, sens, mask, stream), ksp

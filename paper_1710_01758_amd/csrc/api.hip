@@ -196,6 +196,21 @@ hipError_t launch_operator(pics_ctx* c, const pics_ctx::Group& g, int mode, int 
                           g.coil_groups, c->dpart, c->img_total);
 }
 
+}  // namespace
+
+// twiddles tw[k] = exp(-2 pi i k / N), computed in double
+void pics::fill_twiddles(float2* tw) {
+  for (int N : kSupportedSizes) {
+    const int off = tw_offset(N);
+    for (int k = 0; k < N; ++k) {
+      const double a = -2.0 * M_PI * (double)k / (double)N;
+      tw[off + k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+  }
+}
+
+namespace {
+
 bool levels_ok(int m, int n, int levels) {
   for (int l = 0; l < levels; ++l) {
     if ((m >> l) % 2 || (n >> l) % 2 || (m >> l) < 2 || (n >> l) < 2) return false;
@@ -430,15 +445,8 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
     return PICS_ERR_HIP;
   }
 
-  // twiddles tw[k] = exp(-2 pi i k / N), computed in double
   std::vector<float2> tw(kTwiddleTotal);
-  for (int N : kSupportedSizes) {
-    const int off = tw_offset(N);
-    for (int k = 0; k < N; ++k) {
-      const double a = -2.0 * M_PI * (double)k / (double)N;
-      tw[off + k] = make_float2((float)std::cos(a), (float)std::sin(a));
-    }
-  }
+  fill_twiddles(tw.data());
   std::vector<int> all(nslices);
   for (int s = 0; s < nslices; ++s) all[s] = s;
   bool ok = hipMemcpy(c->tw, tw.data(), sizeof(float2) * kTwiddleTotal, hipMemcpyHostToDevice) == hipSuccess &&

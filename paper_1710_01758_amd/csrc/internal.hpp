@@ -157,6 +157,29 @@ hipError_t launch_build_k2d(const Simple& S, const Ws& w, const float2* a, const
 hipError_t launch_coil_compress(const Simple& S, const Ws& w, const float2* ksp, const float2* sens, int nvirt,
                                 double2* scratch, float2* ksp_out, float2* sens_out);
 
+// ---- 3D extension (k_volume.hip); V voxels, nc coil volumes back to back
+constexpr int kVolDotBlocks = 256;
+hipError_t launch3_coil_mul(hipStream_t st, const float2* S, const float2* x, float2* out, int nc, long long V);
+hipError_t launch3_mask_scale(hipStream_t st, float2* buf, const uint8_t* mask, int nc, long long V, float scale);
+hipError_t launch3_accumulate(hipStream_t st, const float2* S, const float2* buf, const float2* x, float2* y, int nc,
+                              int p, int m, int n, float mu, float lam, float gam, int data);
+hipError_t launch3_power(hipStream_t st, const float2* buf, float* P, int nc, long long V);
+hipError_t launch3_corr_prep(hipStream_t st, const uint8_t* mask, const float* P, float2* a, float2* b, long long V);
+hipError_t launch3_corr_mul(hipStream_t st, float2* a, const float2* b, long long V);
+hipError_t launch3_build_k(hipStream_t st, const float2* a, float* kraw, float* kinv, int* bad, int p, int m, int n,
+                           double mu, double lam, double gam);
+hipError_t launch3_scale(hipStream_t st, float2* buf, const float* s, long long V);
+// scal[idx] = Re(a^H b) in FP64 (partials in part[slot][kVolDotBlocks], fixed-order sum)
+hipError_t launch3_dot(hipStream_t st, const float2* a, const float2* b, long long V, double* part, int slot,
+                       double* scal, int idx);
+hipError_t launch3_residual(hipStream_t st, const float2* b, const float2* q, float2* r, long long V);
+hipError_t launch3_update_xr(hipStream_t st, float2* x, float2* r, const float2* p, const float2* q, const double* scal,
+                             int irho, int isig, long long V);
+hipError_t launch3_update_p(hipStream_t st, float2* p, const float2* z, const double* scal, int inew, int iold,
+                            long long V);
+// packed twiddle tables tw[tw_offset(N) + k] = exp(-2 pi i k / N) (host, FP64 rounded)
+void fill_twiddles(float2* tw_host);
+
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
 hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,

@@ -1,0 +1,110 @@
+"""GPU parity of the 3D extension against the FP64 oracle: the 3D system
+operator, the 3D circulant spectrum and M^-1, and PCG (iteration-locked and
+free-running, none / circulant) on seeded volumes."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pcg as opcg
+from oracle import volume as ov
+from paper_1710_01758_amd import inputs as gen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+SMALL = gen.VolumeSpec(64, 64, 64, 4, 4.0, 8)
+LARGE = gen.VolumeSpec(64, 128, 128, 8, 4.0, 12)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a ROCm device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1710_01758_amd import binding
+    binding.lib()
+    return binding
+
+
+def _rand(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("spec", [SMALL, LARGE], ids=["64x64x64x4", "64x128x128x8"])
+def test_volume_operator_spectrum_and_minv(torch, B, spec):
+    _say(f"3D {spec.p}x{spec.m}x{spec.n}: operator, k, M^-1")
+    it = gen.make_volume_instance(spec, gen.eval_seed(8))
+    vol, _ = B.volume_for(it)
+    shape = (spec.p, spec.m, spec.n)
+    x = _rand(shape, 1)
+    xd = B.to_device(x.astype(np.complex64).ravel())
+    yd = torch.empty_like(xd)
+    vol.apply_A(xd, yd)
+    r3 = it.mask.astype(np.float64)
+    ref = ov.apply_A3(x, it.sens, r3, spec.mu, spec.lam, spec.gam)
+    err = H.rel_err(yd.cpu().numpy().reshape(shape), ref)
+    _say(f"  operator rel err {err:.2e}")
+    assert err < 1e-5
+    khat = torch.empty(vol.voxels, dtype=torch.float32, device="cuda")
+    vol.build_preconditioner("circulant", khat=khat)
+    k = ov.circulant_k3(it.sens, r3, spec.mu, spec.lam, spec.gam)
+    kerr = np.max(np.abs(khat.cpu().numpy().reshape(shape) - k)) / k.max()
+    _say(f"  k max rel err {kerr:.2e}")
+    assert kerr < 1e-5
+    zd = torch.empty_like(xd)
+    vol.apply_Minv(xd, zd)
+    assert H.rel_err(zd.cpu().numpy().reshape(shape), ov.apply_minv3(x, k)) < 1e-5
+    vol.close()
+
+
+@pytest.mark.parametrize("kind", ["circulant", "none"])
+def test_volume_pcg_locked_and_free_running(torch, B, kind):
+    _say(f"3D PCG {kind}")
+    spec = SMALL
+    it = gen.make_volume_instance(spec, gen.eval_seed(8))
+    shape = (spec.p, spec.m, spec.n)
+    r3 = it.mask.astype(np.float64)
+    A = lambda v: ov.apply_A3(v, it.sens, r3, spec.mu, spec.lam, spec.gam)
+    b = spec.mu * np.sum(np.conj(it.sens) * ov.ifft3u(it.kspace), axis=0)
+    k = ov.circulant_k3(it.sens, r3, spec.mu, spec.lam, spec.gam)
+    minv = (lambda v: ov.apply_minv3(v, k)) if kind == "circulant" else None
+    ref = opcg.pcg(A, b, np.zeros_like(b), minv, 1e-3, 500)
+    vol, ksp = B.volume_for(it)
+    vol.build_preconditioner(kind)
+    bd = torch.empty(vol.voxels, dtype=torch.complex64, device="cuda")
+    vol.rhs(ksp, bd)  # the right-hand side on the GPU, against the oracle's
+    assert H.rel_err(bd.cpu().numpy().reshape(shape), b) < 1e-5
+    xd = torch.zeros_like(bd)
+    iters, rel, rc = vol.pcg_solve(bd, xd, 0.0, ref.iters)
+    assert iters == ref.iters
+    err = H.rel_err(xd.cpu().numpy().reshape(shape), ref.x)
+    _say(f"  {ref.iters} iterations locked, rel err {err:.2e}")
+    assert err < 1e-4
+    xd.zero_()
+    iters, rel, rc = vol.pcg_solve(bd, xd, 1e-3, 500)
+    assert rc == B.PICS_OK and abs(iters - ref.iters) <= 1
+    xg = xd.cpu().numpy().reshape(shape).astype(np.complex128)
+    assert np.linalg.norm(b - A(xg)) / np.linalg.norm(b) <= 1.05e-3
+    vol.close()
+
+
+def test_volume_zero_rhs(torch, B):
+    it = gen.make_volume_instance(SMALL, gen.eval_seed(8))
+    vol, _ = B.volume_for(it)
+    vol.build_preconditioner("circulant")
+    b = torch.zeros(vol.voxels, dtype=torch.complex64, device="cuda")
+    x = torch.ones_like(b)
+    iters, rel, rc = vol.pcg_solve(b, x, 1e-3, 10)
+    assert iters == 0 and float(x.abs().max()) == 0.0
+    vol.close()
