@@ -178,3 +178,13 @@ def test_line_mask_data_term_is_one_dimensional():
     full = ops.ifft2u(ops.as_mask2d(r, m, n) * ops.fft2u(v))
     oned = np.fft.ifft(r[:, None] * np.fft.fft(v, axis=0), axis=0)
     assert np.allclose(full, oned, atol=1e-14)
+
+
+def test_daubechies_4_matches_the_published_table():
+    """The oracle derives db4 by spectral factorisation; the published values
+    (tests/golden, Daubechies' Table 6.1) pin it from outside."""
+    import pathlib
+    path = pathlib.Path(__file__).parent / "golden" / "db4_lowpass_table_6_1.txt"
+    ref = np.array([float(l) for l in path.read_text().splitlines() if l.strip() and not l.startswith("#")])
+    h4 = np.array(wav.daubechies_lowpass(4))
+    assert np.max(np.abs(h4 - ref)) < 1e-15 * 10
