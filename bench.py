@@ -459,7 +459,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (fp32) with fp64 reductions",
+        "dtype": "c64",
+        "dtype_note": "complex64 (FP32) vectors and transforms, FP64 inner products and PCG scalars",
         "data": "synthetic",
         "config": {"workload": f"split_bregman_recon 256x256, 12 coils, R=4 lines (24 centre), TV + db4 x3, "
                                f"mu=1e-3 lambda=gamma=4e-3, 20 outer iters, PCG tol 1e-3, circulant; "
