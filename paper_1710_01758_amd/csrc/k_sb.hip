@@ -254,6 +254,51 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
   const bool lastlev = (a.level == sd.levels - 1);
   const bool small = ml < kWIn || nl < kWIn;
   const Filt<K> f;
+  // Every operand the kernel will need besides the input tile is requested
+  // first, so that it is in flight during the tile load and both passes:
+  // the Bregman variables of the outputs (shrink mode) and, at level 0, the
+  // TV and outer-update operands of the 2 kWT x 2 kWT pixel block.
+  constexpr int PER = kWT * 2 * kWT / kWThreads;
+  float2 blo[PER] = {}, bhi[PER] = {};
+  if (a.mode == 1) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      const int k = idx / (2 * kWT), cp = idx % (2 * kWT);
+      const int half = cp / kWT, gk = k0 + k, gc = c0 + (cp % kWT);
+      if (gk < mh && gc < nh) {
+        const long long plo = o + (long long)gk * n + half * nh + gc;
+        const long long phi = o + (long long)(mh + gk) * n + half * nh + gc;
+        if (!(half == 0 && !lastlev)) blo[e] = a.bw[plo];
+        bhi[e] = a.bw[phi];
+      }
+    }
+  }
+  constexpr int PER_TV = 4 * kWT * kWT / kWThreads;
+  const OuterArgs& oa = tv.outer;
+  const bool tv_here = tv.enabled && a.level == 0;
+  float2 bxs[PER_TV], bys[PER_TV], obs[PER_TV], ors[PER_TV], ogs[PER_TV] = {}, og1s[PER_TV] = {};
+  if (tv_here) {
+#pragma unroll
+    for (int e = 0; e < PER_TV; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
+      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+      if (i < ml && jj < nl) {
+        const long long pp = o + (long long)i * n + jj;
+        bxs[e] = tv.bx[pp];
+        bys[e] = tv.by[pp];
+        if (oa.mode) {
+          obs[e] = oa.b[pp];
+          ors[e] = oa.r[pp];
+          if (oa.mode == 2) {
+            ogs[e] = oa.g[pp];
+            og1s[e] = oa.g1[pp];
+          }
+        }
+      }
+    }
+  }
   {
     // every load of the thread in flight at once, then the LDS stores
     constexpr int PER = (kWIn * kWIn + kWThreads - 1) / kWThreads;
@@ -289,22 +334,6 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
   }
   __syncthreads();
   // along axis 0, then the band placement (Mallat layout)
-  constexpr int PER = kWT * 2 * kWT / kWThreads;
-  float2 blo[PER] = {}, bhi[PER] = {};  // Bregman variables of the outputs (shrink mode), loaded up front
-  if (a.mode == 1) {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int idx = threadIdx.x + kWThreads * e;
-      const int k = idx / (2 * kWT), cp = idx % (2 * kWT);
-      const int half = cp / kWT, gk = k0 + k, gc = c0 + (cp % kWT);
-      if (gk < mh && gc < nh) {
-        const long long plo = o + (long long)gk * n + half * nh + gc;
-        const long long phi = o + (long long)(mh + gk) * n + half * nh + gc;
-        if (!(half == 0 && !lastlev)) blo[e] = a.bw[plo];
-        bhi[e] = a.bw[phi];
-      }
-    }
-  }
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int idx = threadIdx.x + kWThreads * e;
@@ -327,28 +356,7 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
   // level 0: Algorithm 1 steps 6, 7, 9, 10 on the 2 kWT x 2 kWT pixel block
   if (tv.enabled && a.level == 0) {
     const float thr = 1.0f / sd.lam;
-    constexpr int PER = 4 * kWT * kWT / kWThreads;
-    const OuterArgs& oa = tv.outer;
-    float2 bxs[PER], bys[PER], obs[PER], ors[PER], ogs[PER] = {}, og1s[PER] = {};
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int idx = threadIdx.x + kWThreads * e;
-      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
-      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
-      if (i < ml && jj < nl) {
-        const long long pp = o + (long long)i * n + jj;
-        bxs[e] = tv.bx[pp];
-        bys[e] = tv.by[pp];
-        if (oa.mode) {
-          obs[e] = oa.b[pp];
-          ors[e] = oa.r[pp];
-          if (oa.mode == 2) {
-            ogs[e] = oa.g[pp];
-            og1s[e] = oa.g1[pp];
-          }
-        }
-      }
-    }
+    constexpr int PER = PER_TV;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int idx = threadIdx.x + kWThreads * e;
@@ -409,6 +417,27 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
   const bool lastlev = (a.level == sd.levels - 1);
   const bool small = mh < kWB || nh < kWB;
   const Filt<K> f;
+  // the right-hand side's operands (level 0, mode 1) are requested first so
+  // that they are in flight during the band loads and both filter passes
+  constexpr int PER = 4 * kWT * kWT / kWThreads;
+  const bool rhs_mode = a.level == 0 && a.mode == 1;
+  float2 rg[PER], rx0[PER], rx1[PER], ry0[PER], ry1[PER];
+  if (rhs_mode) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
+      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+      if (i < ml && jj < nl) {
+        const long long p = o + (long long)i * n + jj;
+        rg[e] = a.g[p];
+        rx0[e] = a.ux[p];
+        rx1[e] = a.ux[o + (long long)((i + 1) % sd.m) * n + jj];
+        ry0[e] = a.uy[p];
+        ry1[e] = a.uy[o + (long long)i * n + (jj + 1) % n];
+      }
+    }
+  }
   {
     constexpr int NB = 4 * kWB * kWB;
     constexpr int PER = (NB + kWThreads - 1) / kWThreads;
@@ -449,25 +478,6 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
   }
   __syncthreads();
   // along axis 1
-  constexpr int PER = 4 * kWT * kWT / kWThreads;
-  const bool rhs_mode = a.level == 0 && a.mode == 1;
-  float2 rg[PER], rx0[PER], rx1[PER], ry0[PER], ry1[PER];  // right-hand-side operands, loaded up front
-  if (rhs_mode) {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int idx = threadIdx.x + kWThreads * e;
-      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
-      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
-      if (i < ml && jj < nl) {
-        const long long p = o + (long long)i * n + jj;
-        rg[e] = a.g[p];
-        rx0[e] = a.ux[p];
-        rx1[e] = a.ux[o + (long long)((i + 1) % sd.m) * n + jj];
-        ry0[e] = a.uy[p];
-        ry1[e] = a.uy[o + (long long)i * n + (jj + 1) % n];
-      }
-    }
-  }
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int idx = threadIdx.x + kWThreads * e;
