@@ -239,6 +239,7 @@ int wavelet_analysis(pics_ctx* c, const float2* in, int mode, float2* coef, floa
     a.uw = uw;
     TvArgs t = tv;
     t.enabled = (l == 0) ? tv.enabled : 0;
+    if (l > 0) t.outer.rec = SolveRecord{};
     const hipError_t e = launch_wavelet(S, w, a, t, c->wave_tiles[l]);
     if (e != hipSuccess) return fail(c, PICS_ERR_HIP, "wavelet analysis: %s", hipGetErrorString(e));
   }
@@ -603,7 +604,7 @@ int apply_Minv(pics_ctx* c, const void* r, void* z) {
   GroupFork fk(c);
   for (auto& g : c->groups) {
     HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 0, 0, (const float2*)r, c->t));
-    HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 0, 0, 0.0, c->t));
+    HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 0, 0, 0.0, c->t, nullptr));
     HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 0, c->t, (float2*)z));
   }
   HIPCHK(c, fk.join());
@@ -665,18 +666,16 @@ int enq_pcg_setup(pics_ctx* c, const float2* b, float2* x, double tol, int maxit
         HIPCHK(c, launch_operator(c, g, CA_APPLY, TERM_ALL, pk, tol, x, nullptr, nullptr, nullptr, c->q));
       HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_SETUP, pk, b, c->q, x, c->r, nullptr, nullptr,
                                   c->t, maxit, maxit_dev));
+      if (circ) {
+        // the set-up's stop test (zero right-hand side included) runs at
+        // the start of the preconditioner's middle pass
+        HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 2, tol, c->t, x));
+        HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
+      }
     }
     HIPCHK(c, fk.join());
   }
-  HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 1, x));
-  if (circ) {
-    GroupFork fk(c);
-    for (auto& g : c->groups) {
-      HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
-      HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
-    }
-    HIPCHK(c, fk.join());
-  }
+  if (!circ) HIPCHK(c, launch_pcg_check(c->stream, w, c->nslices, tol, 1, x));
   return PICS_OK;
 }
 
@@ -697,7 +696,7 @@ int enq_pcg_iters(pics_ctx* c, float2* x, double tol, int k0, int count) {
       HIPCHK(c, launch_row_update(make_launch(c, g), ws_for(c, g), RU_UPDATE, pk, nullptr, c->q, x, c->r, pnew,
                                   nullptr, c->t));
       if (circ) {
-        HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t));
+        HIPCHK(c, launch_col_precond(make_launch(c, g), ws_for(c, g), 1, 1, tol, c->t, nullptr));
         HIPCHK(c, launch_row_z(make_launch(c, g), ws_for(c, g), c->t, c->r, c->z));
       }
     }
@@ -782,11 +781,15 @@ int enq_rhs(pics_ctx* c) {
 // solve's x, with the outer update fused in: q = A x = b - r for the next
 // solve's set-up, and, after the last inner solve of an outer iteration
 // (outer_step), steps 13-15 in the image domain, g <- g + g_1 - A_data x.
-int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step) {
+// `rec` (optional) is the solve's end record, taken by the first kernel.
+int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step, const SolveRecord& rec = SolveRecord{}) {
   const Ws w = make_ws(c);
   const Simple S = make_simple(c);
-  const OuterArgs oa{outer_step ? 2 : 1, c->rhs, c->r, c->q, c->g, c->g1};
-  if (c->any_nowavelet) HIPCHK(c, launch_tv_shrink(S, w, 1, oa, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+  OuterArgs oa{outer_step ? 2 : 1, c->rhs, c->r, c->q, c->g, c->g1, rec};
+  if (c->any_nowavelet) {
+    HIPCHK(c, launch_tv_shrink(S, w, 1, oa, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+    oa.rec = SolveRecord{};
+  }
   if (c->any_wavelet) {
     TvArgs tv{1, c->bx, c->by, c->ux, c->uy, oa};
     return wavelet_analysis(c, x, 1, nullptr, c->bw, c->uw, tv);
@@ -797,7 +800,6 @@ int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step) {
 // One outer iteration (all inner iterations) with fixed-budget PCG solves,
 // each followed by a record of its per-slice iteration count and status.
 int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
-  const Ws w = make_ws(c);
   for (int ji = 0; ji < n_inner; ++ji) {
     int rc = enq_rhs(c);
     if (rc) return rc;
@@ -805,9 +807,8 @@ int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner
     if (rc) return rc;
     rc = enq_pcg_iters(c, x, tol, 0, budget);
     if (rc) return rc;
-    HIPCHK(c, launch_pcg_finish(c->stream, w, c->nslices, tol, c->hist, c->hist + c->hist_cap / 2,
-                                c->solve_counter));
-    rc = enq_shrinks(c, x, ji == n_inner - 1);
+    const SolveRecord rec{c->hist, c->hist + c->hist_cap / 2, c->solve_counter, tol, c->nslices};
+    rc = enq_shrinks(c, x, ji == n_inner - 1, rec);
     if (rc) return rc;
   }
   return PICS_OK;

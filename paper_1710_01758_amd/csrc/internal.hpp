@@ -5,7 +5,11 @@
 
 namespace pics {
 
-constexpr int kColT = 16;     // columns per column tile (8 for columns of length 1024)
+// columns per column tile (8 for columns of length 1024); a build option
+#ifndef PICS_COLT
+#define PICS_COLT 16
+#endif
+constexpr int kColT = PICS_COLT;
 __host__ __device__ constexpr int col_tile(int m) { return m >= 1024 ? 8 : kColT; }
 constexpr int kRowRR = 16;    // rows per row tile
 constexpr int kPartMax = 128;  // partial sums per slice per reduction
@@ -94,6 +98,18 @@ struct WaveArgs {
 // Image-domain outer update fused into the shrink kernels (level 0):
 // mode 1: q = b - r (= A x after the solve that produced r);
 // mode 2: also g <- g + g1 - A_data x with A_data x = q - lam L x - gam x.
+// End-of-solve record of a fixed-budget solve (graph replays), carried by the
+// first shrink kernel after the solve: every slice's stop test, then its
+// iteration count and status stored at row *counter of the history; then the
+// counter advances.  counter == nullptr: no record.
+struct SolveRecord {
+  int* iters;
+  int* status;
+  int* counter;
+  double tol;
+  int nslices;
+};
+
 struct OuterArgs {
   int mode;
   const float2* b;
@@ -101,6 +117,7 @@ struct OuterArgs {
   float2* q;
   float2* g;
   const float2* g1;
+  SolveRecord rec;
 };
 
 struct TvArgs {
@@ -132,7 +149,8 @@ hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, i
 hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, const float2* b, const float2* q,
                              float2* x, float2* r, const float2* pn, float2* p, float2* t, int maxit = 0,
                              const int* maxit_ps = nullptr);
-hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t);
+hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t,
+                              float2* x);
 hipError_t launch_row_z(const Launch& L, const Ws& w, const float2* t, const float2* r, float2* z);
 hipError_t launch_row_fft(const Launch& L, const Ws& w, int inverse, int ncoil_mode, const float2* in, float2* out);
 hipError_t launch_col_fft(const Launch& L, const Ws& w, int inverse, const float2* in, float2* out);
@@ -196,8 +214,6 @@ hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v);
 hipError_t launch_add_gamma(const Simple& S, const Ws& w, const float2* wx, const float2* x, float2* y);
 // end-of-solve stop test of every slice, then the per-slice iteration count
 // and status recorded at history row *counter (the counter advances)
-hipError_t launch_pcg_finish(hipStream_t st, const Ws& w, int nslices, double tol, int* hist_iters,
-                             int* hist_status, int* counter);
 hipError_t launch_set_int(hipStream_t st, int* p, int v);
 
 }  // namespace pics

@@ -36,14 +36,15 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
   constexpr int TS = T + 2;  // tile stride with the two halo columns
   constexpr int HP = (2 * M + TH - 1) / TH;
   constexpr bool DUAL = ApplyDual<M>::value;
-  __shared__ float2 lds[DUAL ? 2 * M * T : M * TS];
+  constexpr int LB = ColLay<T>::template size<M>;  // one exchange buffer
+  __shared__ float2 lds[DUAL ? (2 * LB > M * TS ? 2 * LB : M * TS) : (LB > M * TS ? LB : M * TS)];
   __shared__ float2 s_tw[M];
   __shared__ double red[16];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
   const int n = sd.n;
   const int j = threadIdx.x % T, t = threadIdx.x / T;
-  const int j0 = blockIdx.x * T;
+  const int j0 = xcd_tile(blockIdx.x, gridDim.x) * T;
   const int col = j0 + j;
   // CA_PCG in the finishing pass: p was written to pn by the partial pass
   const float2* __restrict__ xs = (MODE == CA_PCG ? (const float2*)pn : xin) + sd.img;
@@ -70,59 +71,65 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
   }
   stage_twiddles<M, TH>(s_tw, w.tw);
 
-  // p for the tile (cyclic rows) and the two halo columns, loads batched
-  const int jl = (j0 - 1 + n) % n, jr = (j0 + T) % n;
-  int hoff[HP];
-#pragma unroll
-  for (int k = 0; k < HP; ++k) {
-    const int h = threadIdx.x + k * TH;
-    const int side = h / M, i = h % M;
-    hoff[k] = h < 2 * M ? i * n + (side ? jr : jl) : 0;
-  }
+  // p for the tile (cyclic rows); the two halo columns are loaded with it,
+  // or after the coil loop for narrow tiles (more halo values per thread)
+  const float2* __restrict__ zs = zsrc + sd.img;
+  const float2* __restrict__ po = pold + sd.img;
+  const float* __restrict__ jc = w.jac + sd.img;
   float2 pv[E], ph[HP];
-  if (MODE != CA_PCG || PH == AP_FIN) {
+  auto load_halo = [&]() {
+    const int jl = (j0 - 1 + n) % n, jr = (j0 + T) % n;
+    int hoff[HP];
 #pragma unroll
-    for (int e = 0; e < E; ++e) pv[e] = xs[(t + NT * e) * n + col];
-    if (PH != AP_PART) {
-#pragma unroll
-      for (int k = 0; k < HP; ++k) ph[k] = xs[hoff[k]];
+    for (int k = 0; k < HP; ++k) {
+      const int h = threadIdx.x + k * TH;
+      const int side = h / M, i = h % M;
+      hoff[k] = h < 2 * M ? i * n + (side ? jr : jl) : 0;
     }
-  } else {
-    const float2* __restrict__ zs = zsrc + sd.img;
-    const float2* __restrict__ po = pold + sd.img;
-    const float* __restrict__ jc = w.jac + sd.img;
-    constexpr bool halo = PH == AP_FUSED;
+    if (MODE != CA_PCG || PH == AP_FIN) {
+      if (PH != AP_PART) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) pv[e] = zs[(t + NT * e) * n + col];
-    if (halo) {
+        for (int k = 0; k < HP; ++k) ph[k] = xs[hoff[k]];
+      }
+    } else if (PH == AP_FUSED) {
 #pragma unroll
       for (int k = 0; k < HP; ++k) ph[k] = zs[hoff[k]];
-    }
-    if (pk == PK_JACOBI) {
-      float jv[E], jh[HP];
-#pragma unroll
-      for (int e = 0; e < E; ++e) jv[e] = jc[(t + NT * e) * n + col];
-#pragma unroll
-      for (int e = 0; e < E; ++e) pv[e] = cscale(pv[e], jv[e]);
-      if (halo) {
+      if (pk == PK_JACOBI) {
+        float jh[HP];
 #pragma unroll
         for (int k = 0; k < HP; ++k) jh[k] = jc[hoff[k]];
 #pragma unroll
         for (int k = 0; k < HP; ++k) ph[k] = cscale(ph[k], jh[k]);
       }
-    }
-    if (!first) {
-      float2 ov[E], oh[HP];
-#pragma unroll
-      for (int e = 0; e < E; ++e) ov[e] = po[(t + NT * e) * n + col];
-#pragma unroll
-      for (int e = 0; e < E; ++e) pv[e] = make_float2(pv[e].x + beta * ov[e].x, pv[e].y + beta * ov[e].y);
-      if (halo) {
+      if (!first) {
+        float2 oh[HP];
 #pragma unroll
         for (int k = 0; k < HP; ++k) oh[k] = po[hoff[k]];
 #pragma unroll
         for (int k = 0; k < HP; ++k) ph[k] = make_float2(ph[k].x + beta * oh[k].x, ph[k].y + beta * oh[k].y);
       }
+    }
+  };
+  constexpr bool LATE_HALO = HP > 4;
+  if (MODE != CA_PCG || PH == AP_FIN) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) pv[e] = xs[(t + NT * e) * n + col];
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) pv[e] = zs[(t + NT * e) * n + col];
+    if (pk == PK_JACOBI) {
+      float jv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) jv[e] = jc[(t + NT * e) * n + col];
+#pragma unroll
+      for (int e = 0; e < E; ++e) pv[e] = cscale(pv[e], jv[e]);
+    }
+    if (!first) {
+      float2 ov[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) ov[e] = po[(t + NT * e) * n + col];
+#pragma unroll
+      for (int e = 0; e < E; ++e) pv[e] = make_float2(pv[e].x + beta * ov[e].x, pv[e].y + beta * ov[e].y);
     }
     if (PH == AP_FUSED || blockIdx.z == 0) {
       float2* __restrict__ pno = pn + sd.img;
@@ -130,6 +137,7 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
       for (int e = 0; e < E; ++e) pno[(t + NT * e) * n + col] = pv[e];
     }
   }
+  if (!LATE_HALO) load_halo();
   // data term sum_c conj(S_c) F^H R F (S_c p), coil maps of c + 1 in flight.
   // AP_PART: coils c = z, z + ngroups, ... of group z = blockIdx.z, result to
   // dpart[z]; AP_FIN: the groups' partial sums added in group order.
@@ -175,10 +183,10 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
       if constexpr (DUAL) {
         // exchanges alternate between the two buffers across both transforms
         constexpr bool odd = (kExchanges<M> & 1) != 0;
-        fft_dual<M, -1, ColLay<T>>(v, t, lds, lds + M * T, j, s_tw);
+        fft_dual<M, -1, ColLay<T>>(v, t, lds, lds + LB, j, s_tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ((mbits >> e) & 1u) ? inv_m : 0.f);
-        fft_dual<M, +1, ColLay<T>>(v, t, odd ? lds + M * T : lds, odd ? lds : lds + M * T, j, s_tw);
+        fft_dual<M, +1, ColLay<T>>(v, t, odd ? lds + LB : lds, odd ? lds : lds + LB, j, s_tw);
       } else {
         fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
@@ -199,6 +207,7 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
     for (int e = 0; e < E; ++e) dp[(t + NT * e) * n + col] = acc[e];
     return;
   }
+  if (LATE_HALO) load_halo();
   __syncthreads();  // the FFTs are done with the LDS buffer
 
   // Fourier-diagonal terms lam (D_x^H D_x + D_y^H D_y) p + gam p on the tile
@@ -348,29 +357,44 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
 
 // ----------------------------------------------------------------------------
 // Middle pass of M^{-1} = F^H diag(1/k) F: column FFT, scale by 1/(k m n),
-// inverse column FFT, in place.  With `check` the stop rule is tested first.
-// use_state = 0 ignores the PCG control block (stand-alone M^{-1}).
+// inverse column FFT, in place.  With `check` the stop rule is tested first:
+// check 1 inside the iteration, check 2 at the set-up, where a zero
+// right-hand side also stops the solve with x = 0 (every workgroup clears
+// its own columns of x; the control block, just reset by the set-up, is not
+// read, so all workgroups take the same decision).  use_state = 0 ignores the
+// PCG control block (stand-alone M^{-1}).
 // ----------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_precond(Ws w, int use_state, int check, double tol,
-                                                                     float2* __restrict__ tbuf) {
+                                                                     float2* __restrict__ tbuf,
+                                                                     float2* __restrict__ x) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
-  __shared__ float2 lds[M * T];
+  __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
+  const int n = sd.n;
+  const int j = threadIdx.x % T, t = threadIdx.x / T;
+  const int col = xcd_tile(blockIdx.x, gridDim.x) * T + j;
+  const long long base = sd.img;
   if (use_state) {
-    if (w.st[s].done) return;
+    if (check != 2 && w.st[s].done) return;
     int status;
-    if (check && pcg_should_stop(w, s, sd.m, tol, &status)) {
+    bool zero_x = false;
+    if (check == 2) {
+      const double bb = part_sum(part_ptr(w.part, s, P_BB), sd.m / kRowRR);
+      zero_x = bb == 0.0;
+    }
+    if (zero_x || (check && pcg_should_stop(w, s, sd.m, tol, &status))) {
+      if (zero_x) {
+        status = 1;
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[base + (long long)(t + NT * e) * n + col] = make_float2(0.f, 0.f);
+      }
       if (blockIdx.x == 0 && threadIdx.x == 0) pcg_mark_done(w, s, status, tol);
       return;
     }
   }
-  const int n = sd.n;
-  const int j = threadIdx.x % T, t = threadIdx.x / T;
-  const int col = blockIdx.x * T + j;
-  const long long base = sd.img;
   stage_twiddles<M, ColCfg<M>::THREADS>(s_tw, w.tw);
   float2 v[E];
   float kv[E];
@@ -422,7 +446,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_z(Ws w, const float2
 
 // ----------------------------------------------------------------------------
 // Plain row FFT (unnormalised).  ncoil_mode 1: loop over the slice's coils on
-// coil-shaped buffers, zeroing unsampled k-space first (R y before F^H);
+// coil-shaped buffers, zeroing unsampled k-space first (R y before F^H; the
+// unsampled lines of a line mask are skipped, left unwritten in `out`);
 // ncoil_mode 2: the same loop without the mask.
 // ----------------------------------------------------------------------------
 template <int N, int DIR>
@@ -439,21 +464,24 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
   const int ncoil = ncoil_mode ? sd.nc : 1;
   const long long plane = (long long)sd.m * N;
   const uint8_t* mk = w.mask + sd.mask;
+  // an unsampled line of a line mask is neither read nor written: the
+  // column pass that follows treats it as zero
+  const bool dead_row = ncoil_mode == 1 && sd.mask_kind == 0 && mk[i] == 0;
   for (int c = 0; c < ncoil; ++c) {
     const long long rowbase = (ncoil_mode ? sd.coil + c * plane : sd.img) + (long long)i * N;
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      float2 a = in[rowbase + t + NT * e];
-      if (ncoil_mode) {
-        const bool keep = ncoil_mode == 2 || (sd.mask_kind == 0 ? mk[i] != 0 : mk[(long long)i * N + t + NT * e] != 0);
-        if (!keep) a = make_float2(0.f, 0.f);
-      }
+      float2 a = make_float2(0.f, 0.f);
+      if (!dead_row) a = in[rowbase + t + NT * e];
+      if (ncoil_mode == 1 && sd.mask_kind != 0 && mk[(long long)i * N + t + NT * e] == 0) a = make_float2(0.f, 0.f);
       v[e] = a;
     }
     fft<N, DIR, RowLay<N>>(v, t, lds, rr_, s_tw);
+    if (!dead_row) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) out[rowbase + t + NT * e] = v[e];
+      for (int e = 0; e < E; ++e) out[rowbase + t + NT * e] = v[e];
+    }
   }
 }
 
@@ -462,7 +490,7 @@ template <int M, int DIR>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_fft(Ws w, const float2* __restrict__ in,
                                                                 float2* __restrict__ out) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
-  __shared__ float2 lds[M * T];
+  __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -489,7 +517,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
                                                                      float2* __restrict__ g1, float2* __restrict__ g,
                                                                      float2* __restrict__ x) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
-  __shared__ float2 lds[M * T];
+  __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -505,11 +533,20 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
     acc[e] = make_float2(0.f, 0.f);
     sos[e] = 0.f;
   }
+  // line masks: the row pass left unsampled lines unwritten (they are zero)
+  unsigned live = ~0u;
+  if (sd.mask_kind == 0) {
+    const uint8_t* mk = w.mask + sd.mask;
+    live = 0u;
+#pragma unroll
+    for (int e = 0; e < E; ++e) live |= (mk[t + NT * e] ? 1u : 0u) << e;
+  }
   for (int c = 0; c < sd.nc; ++c) {
     const long long cb = sd.coil + (long long)c * M * n;
     float2 v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = coil_rows[cb + (long long)(t + NT * e) * n + col];
+    for (int e = 0; e < E; ++e)
+      v[e] = ((live >> e) & 1u) ? coil_rows[cb + (long long)(t + NT * e) * n + col] : make_float2(0.f, 0.f);
     fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -541,7 +578,7 @@ template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, double* __restrict__ pbar,
                                                                         float* __restrict__ energy) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
-  __shared__ float2 lds[M * T];
+  __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -588,7 +625,7 @@ template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, const float2* __restrict__ coil_rows,
                                                                         float* __restrict__ energy) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
-  __shared__ float2 lds[M * T];
+  __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -677,13 +714,14 @@ hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, con
   return hipGetLastError();
 }
 
-hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t) {
+hipError_t launch_col_precond(const Launch& L, const Ws& w, int use_state, int check, double tol, float2* t,
+                              float2* x) {
   const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                           \
   case M:                                                                                                      \
     hipLaunchKernelGGL(k_col_precond<M>, grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, use_state, check, tol, \
-                       t);                                                                                     \
+                       t, x);                                                                                  \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE

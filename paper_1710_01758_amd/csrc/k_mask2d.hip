@@ -92,7 +92,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_sp(Ws w, int pk, dou
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_mask2d(Ws w, int use_state, float2* __restrict__ coil) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
-  __shared__ float2 lds[M * T];
+  __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
@@ -208,7 +208,7 @@ template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_power2d(Ws w, const float2* __restrict__ coil_rows,
                                                                      float* __restrict__ P, float* __restrict__ energy) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
-  __shared__ float2 lds[M * T];
+  __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];

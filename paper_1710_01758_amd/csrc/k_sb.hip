@@ -69,21 +69,19 @@ __global__ __launch_bounds__(256) void k_pcg_check(Ws w, double tol, int setup, 
   }
 }
 
-// End of a fixed-budget solve (graph replays): every slice's stop test, then
-// its iteration count and status stored at row *counter of the history; then
-// the counter advances.
-__global__ __launch_bounds__(256) void k_pcg_finish(Ws w, int nslices, double tol, int* __restrict__ hist_iters,
-                                                    int* __restrict__ hist_status, int* __restrict__ counter) {
+// End of a fixed-budget solve (graph replays), run by workgroup (0, 0) of the
+// first shrink kernel after the solve (nothing reads the PCG control blocks
+// between the solve and the next set-up).
+__device__ void record_solve(const Ws& w, const SolveRecord& rc) {
   __shared__ int row;
-  if (threadIdx.x == 0) row = *counter;
+  if (threadIdx.x == 0) row = *rc.counter;
   __syncthreads();
-  for (int s = threadIdx.x; s < nslices; s += blockDim.x) {
-    slice_stop_test(w, s, tol, 0);
-    hist_iters[(long long)row * nslices + s] = w.st[s].iters;
-    hist_status[(long long)row * nslices + s] = w.st[s].status;
+  for (int s = threadIdx.x; s < rc.nslices; s += blockDim.x) {
+    slice_stop_test(w, s, rc.tol, 0);
+    rc.iters[(long long)row * rc.nslices + s] = w.st[s].iters;
+    rc.status[(long long)row * rc.nslices + s] = w.st[s].status;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) *counter = row + 1;
+  if (threadIdx.x == 0) *rc.counter = row + 1;
 }
 
 __global__ void k_set_int(int* p, int v) {
@@ -115,6 +113,7 @@ __global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, Out
                                                    float2* __restrict__ bx, float2* __restrict__ by,
                                                    float2* __restrict__ ux, float2* __restrict__ uy,
                                                    float2* __restrict__ bw, float2* __restrict__ uw) {
+  if (oa.rec.counter && blockIdx.x == 0 && blockIdx.y == 0) record_solve(w, oa.rec);
   const int s = blockIdx.y;
   const SliceDev sd = w.sl[s];
   if (only_nowavelet && sd.levels > 0 && sd.wavelet != 0) return;
@@ -392,6 +391,7 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
 __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
   __shared__ float2 tile[kWIn][kWIn + 1];
   __shared__ float2 rowb[kWIn][2 * kWT + 1];
+  if (tv.outer.rec.counter && blockIdx.x == 0 && blockIdx.y == 0) record_solve(w, tv.outer.rec);
   const SliceDev sd = w.sl[blockIdx.y];
   if (sd.wavelet == 0 || a.level >= sd.levels) return;
   const int mh = (sd.m >> a.level) / 2, nh = (sd.n >> a.level) / 2;
@@ -598,12 +598,6 @@ static dim3 simple_grid(const Simple& S) {
 
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x) {
   hipLaunchKernelGGL(k_pcg_check, dim3(nslices), dim3(256), 0, st, w, tol, setup, x);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_finish(hipStream_t st, const Ws& w, int nslices, double tol, int* hist_iters,
-                             int* hist_status, int* counter) {
-  hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(256), 0, st, w, nslices, tol, hist_iters, hist_status, counter);
   return hipGetLastError();
 }
 
