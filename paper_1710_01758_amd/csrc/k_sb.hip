@@ -402,7 +402,9 @@ __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
 
 // Synthesis of one level: a 2 kWT x 2 kWT output pixel block from the four
 // bands' (kWT + 3)^2 coefficient windows; at level 0 in mode 1 the pixel is
-// combined straight into the Split Bregman right-hand side.
+// combined straight into the Split Bregman right-hand side.  Output rows (and
+// columns) 2a and 2a + 1 read the same coefficients, with the even and the
+// odd filter taps, so each work item produces such a pair.
 constexpr int kWB = kWT + 3;
 
 template <int K>
@@ -417,24 +419,28 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
   const bool lastlev = (a.level == sd.levels - 1);
   const bool small = mh < kWB || nh < kWB;
   const Filt<K> f;
+  // pixel pairs (columns 2b, 2b + 1 of the block) per thread in the last pass
+  constexpr int PP = 2 * kWT * kWT / kWThreads;
   // the right-hand side's operands (level 0, mode 1) are requested first so
-  // that they are in flight during the band loads and both filter passes
-  constexpr int PER = 4 * kWT * kWT / kWThreads;
+  // that they are in flight during the band loads and both filter passes;
+  // the workspace images are 16-byte aligned and a pair never wraps
   const bool rhs_mode = a.level == 0 && a.mode == 1;
-  float2 rg[PER], rx0[PER], rx1[PER], ry0[PER], ry1[PER];
+  float4 rg[PP], rx0[PP], rx1[PP], ry0[PP];
+  float2 ry2[PP];
   if (rhs_mode) {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int idx = threadIdx.x + kWThreads * e;
-      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
-      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+    for (int e = 0; e < PP; ++e) {
+      const int pidx = threadIdx.x + kWThreads * e;
+      const int ia = pidx / kWT, b = pidx % kWT;
+      const int i = 2 * k0 + ia, jj = 2 * c0 + 2 * b;
       if (i < ml && jj < nl) {
         const long long p = o + (long long)i * n + jj;
-        rg[e] = a.g[p];
-        rx0[e] = a.ux[p];
-        rx1[e] = a.ux[o + (long long)((i + 1) % sd.m) * n + jj];
-        ry0[e] = a.uy[p];
-        ry1[e] = a.uy[o + (long long)i * n + (jj + 1) % n];
+        const int id = i + 1 == sd.m ? 0 : i + 1, jr = jj + 2 == n ? 0 : jj + 2;
+        rg[e] = *reinterpret_cast<const float4*>(a.g + p);
+        rx0[e] = *reinterpret_cast<const float4*>(a.ux + p);
+        rx1[e] = *reinterpret_cast<const float4*>(a.ux + o + (long long)id * n + jj);
+        ry0[e] = *reinterpret_cast<const float4*>(a.uy + p);
+        ry2[e] = a.uy[o + (long long)i * n + jr];
       }
     }
   }
@@ -460,47 +466,54 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
     }
   }
   __syncthreads();
-  // along axis 0
-  for (int idx = threadIdx.x; idx < 2 * kWT * 2 * kWB; idx += blockDim.x) {
-    const int ia = idx / (2 * kWB), q = idx % (2 * kWB);
+  // along axis 0: rows 2 r and 2 r + 1 of u from band rows r - t + 3
+  for (int idx = threadIdx.x; idx < kWT * 2 * kWB; idx += blockDim.x) {
+    const int r = idx / (2 * kWB), q = idx % (2 * kWB);
     const int a1 = q / kWB, cc = q % kWB;
-    float2 acc = make_float2(0.f, 0.f);
+    float2 ev = make_float2(0.f, 0.f), od = make_float2(0.f, 0.f);
 #pragma unroll
     for (int tt = 0; tt < K / 2; ++tt) {
-      const int t = 2 * tt + (ia & 1);
-      const int rr = (ia - t) / 2 + 3;
-      const float2 lv = bands[a1][rr][cc], hv = bands[2 + a1][rr][cc];
-      const float h = (ia & 1) ? f.h[2 * tt + 1] : f.h[2 * tt];
-      const float g = (ia & 1) ? f.g[2 * tt + 1] : f.g[2 * tt];
-      acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
+      const float2 lv = bands[a1][r - tt + 3][cc], hv = bands[2 + a1][r - tt + 3][cc];
+      ev = make_float2(ev.x + f.h[2 * tt] * lv.x + f.g[2 * tt] * hv.x,
+                       ev.y + f.h[2 * tt] * lv.y + f.g[2 * tt] * hv.y);
+      od = make_float2(od.x + f.h[2 * tt + 1] * lv.x + f.g[2 * tt + 1] * hv.x,
+                       od.y + f.h[2 * tt + 1] * lv.y + f.g[2 * tt + 1] * hv.y);
     }
-    u[ia][q] = acc;
+    u[2 * r][q] = ev;
+    u[2 * r + 1][q] = od;
   }
   __syncthreads();
-  // along axis 1
+  // along axis 1: pixel columns 2 b and 2 b + 1 from u columns b - t + 3
 #pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int idx = threadIdx.x + kWThreads * e;
-    const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
-    const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
+  for (int e = 0; e < PP; ++e) {
+    const int pidx = threadIdx.x + kWThreads * e;
+    const int ia = pidx / kWT, b = pidx % kWT;
+    const int i = 2 * k0 + ia, jj = 2 * c0 + 2 * b;
     if (i >= ml || jj >= nl) continue;
-    float2 acc = make_float2(0.f, 0.f);
+    float2 ev = make_float2(0.f, 0.f), od = make_float2(0.f, 0.f);
 #pragma unroll
     for (int tt = 0; tt < K / 2; ++tt) {
-      const int t = 2 * tt + (jb & 1);
-      const int cc = (jb - t) / 2 + 3;
-      const float2 lv = u[ia][cc], hv = u[ia][kWB + cc];
-      const float h = (jb & 1) ? f.h[2 * tt + 1] : f.h[2 * tt];
-      const float g = (jb & 1) ? f.g[2 * tt + 1] : f.g[2 * tt];
-      acc = make_float2(acc.x + h * lv.x + g * hv.x, acc.y + h * lv.y + g * hv.y);
+      const float2 lv = u[ia][b - tt + 3], hv = u[ia][kWB + b - tt + 3];
+      ev = make_float2(ev.x + f.h[2 * tt] * lv.x + f.g[2 * tt] * hv.x,
+                       ev.y + f.h[2 * tt] * lv.y + f.g[2 * tt] * hv.y);
+      od = make_float2(od.x + f.h[2 * tt + 1] * lv.x + f.g[2 * tt + 1] * hv.x,
+                       od.y + f.h[2 * tt + 1] * lv.y + f.g[2 * tt + 1] * hv.y);
     }
+    const long long p = o + (long long)i * n + jj;
     if (rhs_mode) {
       // Algorithm 1 step 4: g + lam (D_x^H u_x + D_y^H u_y) + gam W^H u_w
-      const float2 dx = csub(rx0[e], rx1[e]), dy = csub(ry0[e], ry1[e]);
-      a.rhs[o + (long long)i * n + jj] = make_float2(rg[e].x + sd.lam * (dx.x + dy.x) + sd.gam * acc.x,
-                                                     rg[e].y + sd.lam * (dx.y + dy.y) + sd.gam * acc.y);
+      const float4 g4 = rg[e], x0 = rx0[e], x1 = rx1[e], y0 = ry0[e];
+      const float2 y2 = ry2[e];
+      const float lam = sd.lam, gam = sd.gam;
+      float4 out;
+      out.x = g4.x + lam * ((x0.x - x1.x) + (y0.x - y0.z)) + gam * ev.x;
+      out.y = g4.y + lam * ((x0.y - x1.y) + (y0.y - y0.w)) + gam * ev.y;
+      out.z = g4.z + lam * ((x0.z - x1.z) + (y0.z - y2.x)) + gam * od.x;
+      out.w = g4.w + lam * ((x0.w - x1.w) + (y0.w - y2.y)) + gam * od.y;
+      *reinterpret_cast<float4*>(a.rhs + p) = out;
     } else {
-      a.out[o + (long long)i * n + jj] = acc;
+      a.out[p] = ev;
+      a.out[p + 1] = od;
     }
   }
 }
