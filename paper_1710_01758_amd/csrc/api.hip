@@ -232,6 +232,7 @@ int wavelet_analysis(pics_ctx* c, const float2* in, int mode, float2* coef, floa
     a.level = l;
     a.inverse = 0;
     a.mode = mode;
+    a.fresh = tv.fresh;
     a.in = l == 0 ? in : ((l - 1) % 2 == 0 ? c->w1 : c->w2);
     a.out = l % 2 == 0 ? c->w1 : c->w2;
     a.coef = coef;
@@ -782,16 +783,18 @@ int enq_rhs(pics_ctx* c) {
 // solve's set-up, and, after the last inner solve of an outer iteration
 // (outer_step), steps 13-15 in the image domain, g <- g + g_1 - A_data x.
 // `rec` (optional) is the solve's end record, taken by the first kernel.
-int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step, const SolveRecord& rec = SolveRecord{}) {
+// `fresh`: the Bregman variables are still zero (first shrink) and not read.
+int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step, const SolveRecord& rec = SolveRecord{},
+                bool fresh = false) {
   const Ws w = make_ws(c);
   const Simple S = make_simple(c);
   OuterArgs oa{outer_step ? 2 : 1, c->rhs, c->r, c->q, c->g, c->g1, rec};
   if (c->any_nowavelet) {
-    HIPCHK(c, launch_tv_shrink(S, w, 1, oa, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+    HIPCHK(c, launch_tv_shrink(S, w, 1, fresh ? 1 : 0, oa, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
     oa.rec = SolveRecord{};
   }
   if (c->any_wavelet) {
-    TvArgs tv{1, c->bx, c->by, c->ux, c->uy, oa};
+    TvArgs tv{1, c->bx, c->by, c->ux, c->uy, oa, fresh ? 1 : 0};
     return wavelet_analysis(c, x, 1, nullptr, c->bw, c->uw, tv);
   }
   return PICS_OK;
@@ -907,19 +910,20 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
       GroupFork fk(c);
       for (auto& g : c->groups) {
         HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, (const float2*)kspace, c->coiltmp));
-        HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, x));
+        HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, c->rhs, x));
       }
       HIPCHK(c, fk.join());
     }
-    for (float2* b : {c->bx, c->by, c->bw, c->ux, c->uy, c->uw})
-      HIPCHK(c, launch_fill(c->stream, b, c->img_total, make_float2(0.f, 0.f)));
+    // b_x = b_y = b_w = 0 and d = 0 at the start: the first right-hand side
+    // is g (written by the initialisation) and the first shrinks read no
+    // Bregman variables
     bool q_valid = false;
     int rc_all = PICS_OK;
     const int host_outer = graph_now ? 1 : n_outer;
     for (int jo = 0; jo < host_outer; ++jo) {
       for (int ji = 0; ji < n_inner; ++ji) {
         const long long solve = (long long)jo * n_inner + ji;
-        int rc = enq_rhs(c);
+        int rc = solve == 0 ? PICS_OK : enq_rhs(c);
         if (rc) return rc;
         if (lock_iters) {
           int mx = 0;
@@ -932,7 +936,7 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
         if (rc > 0) rc_all = rc;
         if (pcg_iters)
           for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
-        rc = enq_shrinks(c, x, ji == n_inner - 1);
+        rc = enq_shrinks(c, x, ji == n_inner - 1, SolveRecord{}, solve == 0);
         if (rc) return rc;
         q_valid = true;  // the shrinks left A x = b - r in q
       }

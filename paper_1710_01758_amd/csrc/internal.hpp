@@ -17,6 +17,15 @@ constexpr int kPartMax = 128;  // partial sums per slice per reduction
 // reduction slots (per slice: kSlots x kPartMax doubles)
 enum PartSlot { P_SIGMA = 0, P_RR = 1, P_BB = 2, P_RHO0 = 3, P_RHO1 = 4, P_AUX = 5, kSlots = 6 };
 
+// Tile of workgroup b (column tiles, wavelet tiles).  Workgroups go to the 8 XCDs in turn (linear
+// id mod 8) and each XCD has its own L2, so each XCD is given a run of
+// adjacent tiles: cache lines shared by neighbouring tiles (the operator's
+// halo columns, tiles narrower than a line) are then fetched into one L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  if (ntiles & 7) return b;
+  return (b & 7) * (ntiles >> 3) + (b >> 3);
+}
+
 struct SliceDev {
   int m, n, nc, mask_kind;  // mask_kind: 0 = line mask uint8[m], 1 = 2D uint8[m][n]
   int wavelet, levels;      // 0 none, 1 haar, 2 db4
@@ -83,6 +92,7 @@ struct Launch {
 // Arguments of one wavelet pass (see k_sb.hip).
 struct WaveArgs {
   int level, inverse, pass, last, mode;  // mode 0: store, 1: SB shrink (analysis) / right-hand side (synthesis)
+  int fresh;                             // shrink: the Bregman variables start at zero (not read)
   const float2* in;
   float2* out;
   float2* coef;
@@ -127,6 +137,7 @@ struct TvArgs {
   float2* ux;
   float2* uy;
   OuterArgs outer;
+  int fresh;  // bx, by start at zero (not read)
 };
 
 struct Simple {
@@ -155,7 +166,7 @@ hipError_t launch_row_z(const Launch& L, const Ws& w, const float2* t, const flo
 hipError_t launch_row_fft(const Launch& L, const Ws& w, int inverse, int ncoil_mode, const float2* in, float2* out);
 hipError_t launch_col_fft(const Launch& L, const Ws& w, int inverse, const float2* in, float2* out);
 hipError_t launch_col_sb_init(const Launch& L, const Ws& w, const float2* coil_rows, float2* g1, float2* g,
-                              float2* x);
+                              float2* rhs, float2* x);
 hipError_t launch_col_coil_power(const Launch& L, const Ws& w, double* pbar, float* energy);
 hipError_t launch_col_coil_energy(const Launch& L, const Ws& w, const float2* coil_rows, float* energy);
 
@@ -200,7 +211,8 @@ void fill_twiddles(float2* tw_host);
 
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
-hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, int fresh, const OuterArgs& oa,
+                            const float2* x,
                             float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw);
 hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, const float2* ux, const float2* uy,
                                 const float2* uw, float2* rhs);

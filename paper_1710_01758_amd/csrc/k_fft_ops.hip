@@ -466,10 +466,12 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
   const uint8_t* mk = w.mask + sd.mask;
   // an unsampled line of a line mask is neither read nor written: the
   // column pass that follows treats it as zero
+  // (the next coil's row is loaded while this one is transformed, except at
+  // length 1024, where 1024-thread workgroups leave no registers for it)
+  constexpr bool PF = N < 1024;
   const bool dead_row = ncoil_mode == 1 && sd.mask_kind == 0 && mk[i] == 0;
-  for (int c = 0; c < ncoil; ++c) {
-    const long long rowbase = (ncoil_mode ? sd.coil + c * plane : sd.img) + (long long)i * N;
-    float2 v[E];
+  const long long row0 = (ncoil_mode ? sd.coil : sd.img) + (long long)i * N;
+  auto load_row = [&](long long rowbase, float2 (&v)[E]) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       float2 a = make_float2(0.f, 0.f);
@@ -477,10 +479,21 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
       if (ncoil_mode == 1 && sd.mask_kind != 0 && mk[(long long)i * N + t + NT * e] == 0) a = make_float2(0.f, 0.f);
       v[e] = a;
     }
+  };
+  float2 v[E], vn[E];
+  load_row(row0, v);
+  for (int c = 0; c < ncoil; ++c) {
+    const long long rowbase = row0 + c * plane;
+    if (!PF && c > 0) load_row(rowbase, v);
+    if (PF && c + 1 < ncoil) load_row(rowbase + plane, vn);
     fft<N, DIR, RowLay<N>>(v, t, lds, rr_, s_tw);
     if (!dead_row) {
 #pragma unroll
       for (int e = 0; e < E; ++e) out[rowbase + t + NT * e] = v[e];
+    }
+    if (PF) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = vn[e];
     }
   }
 }
@@ -511,10 +524,12 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_fft(Ws w, const floa
 // first right-hand side): per coil, finish the 2D inverse FFT of R y_c along
 // axis 0 (the row pass already ran), scale to the unitary F^H, and form
 //   g1 = mu sum_c conj(S_c) m_c,   x = sqrt(sum_c |m_c|^2)   (root sum of squares)
+// g = g1, and the first right-hand side, g1 as well (d - b = 0 at the start).
 // ----------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const float2* __restrict__ coil_rows,
                                                                      float2* __restrict__ g1, float2* __restrict__ g,
+                                                                     float2* __restrict__ rhs,
                                                                      float2* __restrict__ x) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T;
   __shared__ float2 lds[ColLay<T>::template size<M>];
@@ -541,20 +556,32 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
 #pragma unroll
     for (int e = 0; e < E; ++e) live |= (mk[t + NT * e] ? 1u : 0u) << e;
   }
-  for (int c = 0; c < sd.nc; ++c) {
-    const long long cb = sd.coil + (long long)c * M * n;
-    float2 v[E];
+  // the coil's maps are requested before its transform, the next coil's
+  // k-space rows while it runs
+  const long long plane = (long long)M * n, off = (long long)t * n + col;
+  float2 v[E], vn[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      v[e] = ((live >> e) & 1u) ? coil_rows[cb + (long long)(t + NT * e) * n + col] : make_float2(0.f, 0.f);
+  for (int e = 0; e < E; ++e)
+    v[e] = ((live >> e) & 1u) ? coil_rows[sd.coil + off + (long long)NT * e * n] : make_float2(0.f, 0.f);
+  for (int c = 0; c < sd.nc; ++c) {
+    const long long cb = sd.coil + c * plane;
+    float2 sv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) sv[e] = w.sens[cb + off + (long long)NT * e * n];
+    if (c + 1 < sd.nc) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        vn[e] = ((live >> e) & 1u) ? coil_rows[cb + plane + off + (long long)NT * e * n] : make_float2(0.f, 0.f);
+    }
     fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const float2 mc = cscale(v[e], scale);
-      const float2 sv = w.sens[cb + (long long)(t + NT * e) * n + col];
-      acc[e] = cadd(acc[e], cconjmul(sv, mc));
+      acc[e] = cadd(acc[e], cconjmul(sv[e], mc));
       sos[e] += cabs2(mc);
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = vn[e];
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -562,6 +589,7 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
     const float2 gv = cscale(acc[e], sd.mu);
     g1[idx] = gv;
     g[idx] = gv;
+    rhs[idx] = gv;
     x[idx] = make_float2(sqrtf(sos[e]), 0.f);
   }
 }
@@ -593,17 +621,28 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, dou
     pw[e] = 0.0;
     en[e] = 0.f;
   }
+  // the next coil's maps are loaded while this coil is transformed
+  const float2* __restrict__ S = w.sens + sd.coil + (long long)t * n + col;
+  const long long plane = (long long)M * n;
+  float2 sv[E], sn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) sv[e] = S[(long long)NT * e * n];
   for (int c = 0; c < sd.nc; ++c) {
-    const long long cb = sd.coil + (long long)c * M * n;
+    if (c + 1 < sd.nc) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) sn[e] = S[(c + 1) * plane + (long long)NT * e * n];
+    }
     float2 v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      v[e] = w.sens[cb + (long long)(t + NT * e) * n + col];
+      v[e] = sv[e];
       en[e] += cabs2(v[e]);
     }
     fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) pw[e] += (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
+#pragma unroll
+    for (int e = 0; e < E; ++e) sv[e] = sn[e];
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -785,12 +824,12 @@ hipError_t launch_col_fft(const Launch& L, const Ws& w, int inverse, const float
 }
 
 hipError_t launch_col_sb_init(const Launch& L, const Ws& w, const float2* coil_rows, float2* g1, float2* g,
-                              float2* x) {
+                              float2* rhs, float2* x) {
   const dim3 grid(L.n / col_tile(L.m), L.count);
   switch (L.m) {
-#define PICS_CASE(M)                                                                                             \
-  case M:                                                                                                        \
-    hipLaunchKernelGGL(k_col_sb_init<M>, grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, coil_rows, g1, g, x); \
+#define PICS_CASE(M)                                                                                                  \
+  case M:                                                                                                             \
+    hipLaunchKernelGGL(k_col_sb_init<M>, grid, dim3(ColCfg<M>::THREADS), 0, L.stream, w, coil_rows, g1, g, rhs, x); \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE

@@ -109,7 +109,8 @@ __device__ __forceinline__ void outer_at(const SliceDev& sd, const OuterArgs& oa
 // v = D x + b;  d = shrink(v, 1/lam);  b <- v - d;  u = d - b (the next
 // right-hand side uses D^H u).  With no wavelet the same is done on x itself
 // with threshold 1/gam.
-__global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, OuterArgs oa, const float2* __restrict__ x,
+__global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, int fresh, OuterArgs oa,
+                                                   const float2* __restrict__ x,
                                                    float2* __restrict__ bx, float2* __restrict__ by,
                                                    float2* __restrict__ ux, float2* __restrict__ uy,
                                                    float2* __restrict__ bw, float2* __restrict__ uw) {
@@ -134,22 +135,23 @@ __global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, Out
       const float2 g1v = oa.mode == 2 ? oa.g1[o + p] : make_float2(0.f, 0.f);
       outer_at(sd, oa, o + p, xc, lap, oa.b[o + p], oa.r[o + p], gv, g1v);
     }
+    const float2 zero = make_float2(0.f, 0.f);
     {
-      const float2 v = cadd(csub(xc, xu), bx[o + p]);
+      const float2 v = cadd(csub(xc, xu), fresh ? zero : bx[o + p]);
       const float2 d = shrink(v, tl);
       const float2 b = csub(v, d);
       bx[o + p] = b;
       ux[o + p] = csub(d, b);
     }
     {
-      const float2 v = cadd(csub(xc, xl), by[o + p]);
+      const float2 v = cadd(csub(xc, xl), fresh ? zero : by[o + p]);
       const float2 d = shrink(v, tl);
       const float2 b = csub(v, d);
       by[o + p] = b;
       uy[o + p] = csub(d, b);
     }
     if (sd.levels == 0 || sd.wavelet == 0) {
-      const float2 v = cadd(xc, bw[o + p]);
+      const float2 v = cadd(xc, fresh ? zero : bw[o + p]);
       const float2 d = shrink(v, tg);
       const float2 b = csub(v, d);
       bw[o + p] = b;
@@ -243,12 +245,12 @@ __device__ __forceinline__ int wrap(int i, int L, bool small) {
 
 template <int K>
 __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs& a, const TvArgs& tv,
-                                             float2 (*tile)[kWIn + 1], float2 (*rowb)[2 * kWT + 1]) {
+                                             float2 (*tile)[kWIn + 1], float2 (*rowb)[2 * kWT + 1], int bt) {
   const int n = sd.n;
   const int ml = sd.m >> a.level, nl = n >> a.level;
   const int mh = ml / 2, nh = nl / 2;
   const int tcols = (nh + kWT - 1) / kWT;
-  const int k0 = (blockIdx.x / tcols) * kWT, c0 = (blockIdx.x % tcols) * kWT;
+  const int k0 = (bt / tcols) * kWT, c0 = (bt % tcols) * kWT;
   const long long o = sd.img;
   const bool lastlev = (a.level == sd.levels - 1);
   const bool small = ml < kWIn || nl < kWIn;
@@ -259,7 +261,7 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
   // TV and outer-update operands of the 2 kWT x 2 kWT pixel block.
   constexpr int PER = kWT * 2 * kWT / kWThreads;
   float2 blo[PER] = {}, bhi[PER] = {};
-  if (a.mode == 1) {
+  if (a.mode == 1 && !a.fresh) {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
       const int idx = threadIdx.x + kWThreads * e;
@@ -276,7 +278,7 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
   constexpr int PER_TV = 4 * kWT * kWT / kWThreads;
   const OuterArgs& oa = tv.outer;
   const bool tv_here = tv.enabled && a.level == 0;
-  float2 bxs[PER_TV], bys[PER_TV], obs[PER_TV], ors[PER_TV], ogs[PER_TV] = {}, og1s[PER_TV] = {};
+  float2 bxs[PER_TV] = {}, bys[PER_TV] = {}, obs[PER_TV], ors[PER_TV], ogs[PER_TV] = {}, og1s[PER_TV] = {};
   if (tv_here) {
 #pragma unroll
     for (int e = 0; e < PER_TV; ++e) {
@@ -285,8 +287,10 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
       const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
       if (i < ml && jj < nl) {
         const long long pp = o + (long long)i * n + jj;
-        bxs[e] = tv.bx[pp];
-        bys[e] = tv.by[pp];
+        if (!tv.fresh) {
+          bxs[e] = tv.bx[pp];
+          bys[e] = tv.by[pp];
+        }
         if (oa.mode) {
           obs[e] = oa.b[pp];
           ors[e] = oa.r[pp];
@@ -395,9 +399,10 @@ __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
   const SliceDev sd = w.sl[blockIdx.y];
   if (sd.wavelet == 0 || a.level >= sd.levels) return;
   const int mh = (sd.m >> a.level) / 2, nh = (sd.n >> a.level) / 2;
-  if ((int)blockIdx.x >= ((nh + kWT - 1) / kWT) * ((mh + kWT - 1) / kWT)) return;
-  if (sd.wavelet == 1) dwt_ana_tile<2>(sd, a, tv, tile, rowb);
-  else dwt_ana_tile<8>(sd, a, tv, tile, rowb);
+  const int bt = xcd_tile(blockIdx.x, gridDim.x);
+  if (bt >= ((nh + kWT - 1) / kWT) * ((mh + kWT - 1) / kWT)) return;
+  if (sd.wavelet == 1) dwt_ana_tile<2>(sd, a, tv, tile, rowb, bt);
+  else dwt_ana_tile<8>(sd, a, tv, tile, rowb, bt);
 }
 
 // Synthesis of one level: a 2 kWT x 2 kWT output pixel block from the four
@@ -409,12 +414,12 @@ constexpr int kWB = kWT + 3;
 
 template <int K>
 __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs& a, float2 (*bands)[kWB][kWB + 1],
-                                             float2 (*u)[2 * kWB + 1]) {
+                                             float2 (*u)[2 * kWB + 1], int bt) {
   const int n = sd.n;
   const int ml = sd.m >> a.level, nl = n >> a.level;
   const int mh = ml / 2, nh = nl / 2;
   const int tcols = (nh + kWT - 1) / kWT;
-  const int k0 = (blockIdx.x / tcols) * kWT, c0 = (blockIdx.x % tcols) * kWT;
+  const int k0 = (bt / tcols) * kWT, c0 = (bt % tcols) * kWT;
   const long long o = sd.img;
   const bool lastlev = (a.level == sd.levels - 1);
   const bool small = mh < kWB || nh < kWB;
@@ -524,9 +529,10 @@ __global__ __launch_bounds__(256) void k_dwt_syn(Ws w, WaveArgs a) {
   const SliceDev sd = w.sl[blockIdx.y];
   if (sd.wavelet == 0 || a.level >= sd.levels) return;
   const int mh = (sd.m >> a.level) / 2, nh = (sd.n >> a.level) / 2;
-  if ((int)blockIdx.x >= ((nh + kWT - 1) / kWT) * ((mh + kWT - 1) / kWT)) return;
-  if (sd.wavelet == 1) dwt_syn_tile<2>(sd, a, bands, u);
-  else dwt_syn_tile<8>(sd, a, bands, u);
+  const int bt = xcd_tile(blockIdx.x, gridDim.x);
+  if (bt >= ((nh + kWT - 1) / kWT) * ((mh + kWT - 1) / kWT)) return;
+  if (sd.wavelet == 1) dwt_syn_tile<2>(sd, a, bands, u, bt);
+  else dwt_syn_tile<8>(sd, a, bands, u, bt);
 }
 
 // ------------------------------------------------------ spectrum assembly
@@ -539,6 +545,8 @@ __global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict_
                                                  float* __restrict__ jac, int* __restrict__ bad) {
   __shared__ double sp[1024];
   __shared__ double skc[1024];
+  __shared__ double sdv[1024];
+  __shared__ int smk[1024];
   __shared__ int ssum;
   const int s = blockIdx.y;
   const SliceDev sd = w.sl[s];
@@ -546,32 +554,44 @@ __global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict_
   const int m = sd.m, n = sd.n;
   const int ntile = n / col_tile(m);
   const uint8_t* mk = w.mask + sd.mask;
+  // this workgroup's rows (the grid has at most m workgroups per slice)
+  const int u0 = (int)((long long)blockIdx.x * m / gridDim.x), u1 = (int)((long long)(blockIdx.x + 1) * m / gridDim.x);
   if (threadIdx.x == 0) ssum = 0;
   __syncthreads();
   int cnt = 0;
   for (int u = threadIdx.x; u < m; u += blockDim.x) {
     double a = 0.0;
+#pragma unroll 16
     for (int tl = 0; tl < ntile; ++tl) a += pbar[sd.aux + (long long)tl * m + u];
     sp[u] = a * n;
+    smk[u] = mk[u] ? 1 : 0;
     cnt += mk[u] ? 1 : 0;
   }
   atomicAdd(&ssum, cnt);
   __syncthreads();
   const double N = (double)m * n;
-  for (int u = threadIdx.x; u < m; u += blockDim.x) {
+  // k_c(u) of this workgroup's rows from the sampled lines, plus the row part
+  // of k_d (2 - 2 cos(2 pi u / m)) and gam; the column part of k_d
+  // (2 - 2 cos(2 pi v / n)) as a table
+  for (int u = u0 + (int)threadIdx.x; u < u1; u += blockDim.x) {
     double a = 0.0;
-    for (int l = 0; l < m; ++l)
-      if (mk[l]) a += sp[(l - u + m) % m];
-    skc[u] = a / (N * N);
+#pragma unroll 16
+    for (int l = 0; l < m; ++l) {
+      const int d = l - u;
+      const double pv = sp[d < 0 ? d + m : d];
+      if (smk[l]) a += pv;
+    }
+    skc[u - u0] = (double)sd.mu * (a / (N * N)) + (double)sd.lam * (2.0 - 2.0 * cospi(2.0 * u / m)) + (double)sd.gam;
   }
+  for (int v = threadIdx.x; v < n; v += blockDim.x) sdv[v] = (double)sd.lam * (2.0 - 2.0 * cospi(2.0 * v / n));
   __syncthreads();
   const double frac = (double)ssum / m;
-  const long long np = (long long)m * n;
+  const long long np = (long long)(u1 - u0) * n;
   int badl = 0;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += (long long)gridDim.x * blockDim.x) {
-    const int u = int(p / n), v = int(p % n);
-    double k = (double)sd.mu * skc[u] +
-               (double)sd.lam * (4.0 - 2.0 * cospi(2.0 * u / m) - 2.0 * cospi(2.0 * v / n)) + (double)sd.gam;
+  for (long long q = threadIdx.x; q < np; q += blockDim.x) {
+    const int du = int(q / n), v = int(q - (long long)du * n);
+    const long long p = (long long)(u0 + du) * n + v;
+    double k = skc[du] + sdv[v];
     if (corr) k *= (double)corr[sd.img + p];
     if (!(k > 0.0) || !isfinite(k)) badl = 1;
     kraw[sd.img + p] = (float)k;
@@ -619,10 +639,10 @@ hipError_t launch_set_int(hipStream_t st, int* p, int v) {
   return hipGetLastError();
 }
 
-hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, const OuterArgs& oa, const float2* x,
-                            float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw) {
-  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, only_nowavelet, oa, x, bx, by, ux, uy,
-                     bw, uw);
+hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, int fresh, const OuterArgs& oa,
+                            const float2* x, float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw) {
+  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, only_nowavelet, fresh, oa, x, bx, by,
+                     ux, uy, bw, uw);
   return hipGetLastError();
 }
 

@@ -35,15 +35,6 @@ struct RowCfg {
   static constexpr int LDS = RR * RowLay<N>::stride;
 };
 
-// Column tile of workgroup b.  Workgroups go to the 8 XCDs in turn (linear
-// id mod 8) and each XCD has its own L2, so each XCD is given a run of
-// adjacent tiles: cache lines shared by neighbouring tiles (the operator's
-// halo columns, tiles narrower than a line) are then fetched into one L2.
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-  if (ntiles & 7) return b;
-  return (b & 7) * (ntiles >> 3) + (b >> 3);
-}
-
 // Stop rule shared by every kernel that tests convergence: relative residual
 // ||r|| <= tol ||b|| (recursive residual), or the per-slice iteration cap.
 __device__ __forceinline__ bool pcg_should_stop(const Ws& w, int s, int m, double tol, int* status) {
