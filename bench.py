@@ -80,7 +80,7 @@ def run_apply_mode(torch, ctx, insts):
                       "achieved_GBs": round(b / t_apply / 1e9, 1), "copy_cal_bytes": COPY_CAL_BYTES}), flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch32_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_hbm_traffic.md")
 
 
 def measured_traffic():
@@ -355,9 +355,9 @@ def learned_section(torch, B, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=32, help="slices reconstructed per step")
+    ap.add_argument("--batch", type=int, default=128, help="slices reconstructed per step")
     ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip training / evaluating the learned correction")

@@ -187,10 +187,10 @@ constexpr int kSupportedSizes[] = {64, 128, 192, 224, 256, 320, 512, 1024};
 // LDS layouts: Lay::addr(idx, seq) gives the slot of element idx of sequence
 // seq.  Column tiles keep T sequences side by side (row-major like global
 // memory); row tiles keep each sequence contiguous with one pad slot per 16.
-// Tiles narrower than 16 columns may pad PICS_COLPAD slots per 16 elements
-// (a build option) to spread the first exchange's stores over the banks.
+// Tiles narrower than 16 columns pad PICS_COLPAD slots per 16 elements (a
+// build option) to spread the first exchange's stores over the banks.
 #ifndef PICS_COLPAD
-#define PICS_COLPAD 0
+#define PICS_COLPAD 4
 #endif
 template <int T>
 struct ColLay {

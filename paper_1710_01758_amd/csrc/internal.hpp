@@ -5,14 +5,16 @@
 
 namespace pics {
 
-// columns per column tile (8 for columns of length 1024); a build option
+// Columns per column tile: 16 up to length 320 (a build option), 4 at 512
+// (a single large slice then still gives the chip enough workgroups), 8 at
+// 1024.
 #ifndef PICS_COLT
 #define PICS_COLT 16
 #endif
 constexpr int kColT = PICS_COLT;
-__host__ __device__ constexpr int col_tile(int m) { return m >= 1024 ? 8 : kColT; }
+__host__ __device__ constexpr int col_tile(int m) { return m >= 1024 ? 8 : m >= 512 ? 4 : kColT; }
 constexpr int kRowRR = 16;    // rows per row tile
-constexpr int kPartMax = 128;  // partial sums per slice per reduction
+constexpr int kPartMax = 256;  // partial sums per slice per reduction (n / col_tile(m) <= 256)
 
 // reduction slots (per slice: kSlots x kPartMax doubles)
 enum PartSlot { P_SIGMA = 0, P_RR = 1, P_BB = 2, P_RHO0 = 3, P_RHO1 = 4, P_AUX = 5, kSlots = 6 };
