@@ -48,7 +48,7 @@ struct pics_ctx {
   void* block = nullptr;
   SliceDev* sl_dev = nullptr;
   float2* tw = nullptr;
-  float2 *r, *t, *z, *p, *pn, *q, *g1, *g, *rhs, *bx, *by, *bw, *ux, *uy, *uw, *w1, *w2;
+  float2 *r, *t, *z, *p, *pn, *q, *g1, *g, *rhs, *bx, *by, *bx2, *by2, *bw, *ux, *uy, *uw, *w1, *w2;
   float2* coiltmp = nullptr;
   float *kraw, *kinv, *jac, *ftmp;
   double *part, *pbar;
@@ -248,10 +248,9 @@ int wavelet_analysis(pics_ctx* c, const float2* in, int mode, float2* coef, floa
 }
 
 // W^H (all levels), coarsest first.  Mode 0 writes the image to `out`;
-// mode 1 writes the Split Bregman right-hand side g + lam (D_x^H u_x +
-// D_y^H u_y) + gam W^H coef into rhs.
-int wavelet_synthesis(pics_ctx* c, const float2* coef, int mode, float2* out, const float2* g, const float2* ux,
-                      const float2* uy, float2* rhs) {
+// mode 1 writes the Split Bregman right-hand side tvr + gam W^H coef into
+// rhs, tvr = g + lam (D_x^H u_x + D_y^H u_y) as the level-0 analysis left it.
+int wavelet_synthesis(pics_ctx* c, const float2* coef, int mode, float2* out, const float2* tvr, float2* rhs) {
   const Ws w = make_ws(c);
   const Simple S = make_simple(c);
   const int L = c->max_levels;
@@ -264,9 +263,7 @@ int wavelet_synthesis(pics_ctx* c, const float2* coef, int mode, float2* out, co
     a.in = l + 1 < L ? buf(l + 1) : nullptr;
     a.out = l == 0 ? out : buf(l);
     a.coef = const_cast<float2*>(coef);
-    a.g = g;
-    a.ux = ux;
-    a.uy = uy;
+    a.tvr = tvr;
     a.rhs = rhs;
     TvArgs t{};
     const hipError_t e = launch_wavelet(S, w, a, t, c->wave_tiles[l]);
@@ -416,7 +413,7 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   for (auto& g : c->groups) add((void**)&g.idx_dev, sizeof(int) * g.idx.size());
   add((void**)&c->tw, sizeof(float2) * kTwiddleTotal);
   float2** cbufs[] = {&c->r, &c->t, &c->z, &c->p, &c->pn, &c->q, &c->g1, &c->g, &c->rhs,
-                      &c->bx, &c->by, &c->bw, &c->ux, &c->uy, &c->uw, &c->w1, &c->w2};
+                      &c->bx, &c->by, &c->bx2, &c->by2, &c->bw, &c->ux, &c->uy, &c->uw, &c->w1, &c->w2};
   for (float2** b : cbufs) add((void**)b, sizeof(float2) * I);
   add((void**)&c->coiltmp, sizeof(float2) * c->coil_total);
   add((void**)&c->kraw, sizeof(float) * I);
@@ -591,7 +588,7 @@ int apply_A(pics_ctx* c, const void* x, void* y, int32_t terms) {
     TvArgs none{};
     int rc = wavelet_analysis(c, (const float2*)x, 0, c->z, nullptr, nullptr, none);
     if (rc) return rc;
-    rc = wavelet_synthesis(c, c->z, 0, c->r, nullptr, nullptr, nullptr, nullptr);
+    rc = wavelet_synthesis(c, c->z, 0, c->r, nullptr, nullptr);
     if (rc) return rc;
     HIPCHK(c, launch_add_gamma(make_simple(c), make_ws(c), c->r, (const float2*)x, (float2*)y));
   }
@@ -637,7 +634,7 @@ int pics_wavelet(pics_ctx* c, const void* in, void* out, int32_t inverse) {
   }
   TvArgs none{};
   if (!inverse) return wavelet_analysis(c, (const float2*)in, 0, (float2*)out, nullptr, nullptr, none);
-  return wavelet_synthesis(c, (const float2*)in, 0, (float2*)out, nullptr, nullptr, nullptr, nullptr);
+  return wavelet_synthesis(c, (const float2*)in, 0, (float2*)out, nullptr, nullptr);
 }
 
 }  // extern "C"
@@ -774,7 +771,8 @@ int enq_rhs(pics_ctx* c) {
   const Ws w = make_ws(c);
   const Simple S = make_simple(c);
   if (c->any_nowavelet) HIPCHK(c, launch_rhs_nowavelet(S, w, c->g, c->ux, c->uy, c->uw, c->rhs));
-  if (c->any_wavelet) return wavelet_synthesis(c, c->uw, 1, nullptr, c->g, c->ux, c->uy, c->rhs);
+  // wavelet slices: the level-0 analysis left g + lam D^H u in c->ux
+  if (c->any_wavelet) return wavelet_synthesis(c, c->uw, 1, nullptr, c->ux, c->rhs);
   return PICS_OK;
 }
 
@@ -783,18 +781,25 @@ int enq_rhs(pics_ctx* c) {
 // solve's set-up, and, after the last inner solve of an outer iteration
 // (outer_step), steps 13-15 in the image domain, g <- g + g_1 - A_data x.
 // `rec` (optional) is the solve's end record, taken by the first kernel.
-// `fresh`: the Bregman variables are still zero (first shrink) and not read.
-int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step, const SolveRecord& rec = SolveRecord{},
-                bool fresh = false) {
+// `solve` counts the solves of the reconstruction: the shrink after solve s
+// reads b_x, b_y from buffer s & 1 and writes buffer (s + 1) & 1; after
+// solve 0 they are still zero and not read.
+int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step, long long solve,
+                const SolveRecord& rec = SolveRecord{}) {
   const Ws w = make_ws(c);
   const Simple S = make_simple(c);
   OuterArgs oa{outer_step ? 2 : 1, c->rhs, c->r, c->q, c->g, c->g1, rec};
+  float2* bxb[2] = {c->bx, c->bx2};
+  float2* byb[2] = {c->by, c->by2};
+  const float2 *bxi = bxb[solve & 1], *byi = byb[solve & 1];
+  float2 *bxo = bxb[(solve + 1) & 1], *byo = byb[(solve + 1) & 1];
+  const int fresh = solve == 0 ? 1 : 0;
   if (c->any_nowavelet) {
-    HIPCHK(c, launch_tv_shrink(S, w, 1, fresh ? 1 : 0, oa, x, c->bx, c->by, c->ux, c->uy, c->bw, c->uw));
+    HIPCHK(c, launch_tv_shrink(S, w, 1, fresh, oa, x, bxi, byi, bxo, byo, c->ux, c->uy, c->bw, c->uw));
     oa.rec = SolveRecord{};
   }
   if (c->any_wavelet) {
-    TvArgs tv{1, c->bx, c->by, c->ux, c->uy, oa, fresh ? 1 : 0};
+    TvArgs tv{1, bxi, byi, bxo, byo, c->ux, oa, fresh};
     return wavelet_analysis(c, x, 1, nullptr, c->bw, c->uw, tv);
   }
   return PICS_OK;
@@ -802,7 +807,8 @@ int enq_shrinks(pics_ctx* c, const float2* x, bool outer_step, const SolveRecord
 
 // One outer iteration (all inner iterations) with fixed-budget PCG solves,
 // each followed by a record of its per-slice iteration count and status.
-int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner, int budget) {
+// jo: index of the outer iteration in the reconstruction.
+int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner, int budget, int jo) {
   for (int ji = 0; ji < n_inner; ++ji) {
     int rc = enq_rhs(c);
     if (rc) return rc;
@@ -811,7 +817,7 @@ int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner
     rc = enq_pcg_iters(c, x, tol, 0, budget);
     if (rc) return rc;
     const SolveRecord rec{c->hist, c->hist + c->hist_cap / 2, c->solve_counter, tol, c->nslices};
-    rc = enq_shrinks(c, x, ji == n_inner - 1, rec);
+    rc = enq_shrinks(c, x, ji == n_inner - 1, (long long)jo * n_inner + ji, rec);
     if (rc) return rc;
   }
   return PICS_OK;
@@ -833,7 +839,8 @@ int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget, int n_
   {
     StreamSwap sw(c, c->cap_stream);
     rc = PICS_OK;
-    for (int k = 0; k < n_rep && rc == PICS_OK; ++k) rc = enq_outer_iteration_budgeted(c, x, tol, n_inner, budget);
+    for (int k = 0; k < n_rep && rc == PICS_OK; ++k)
+      rc = enq_outer_iteration_budgeted(c, x, tol, n_inner, budget, 1 + k);
   }
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
   if (rc) {
@@ -936,7 +943,7 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
         if (rc > 0) rc_all = rc;
         if (pcg_iters)
           for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
-        rc = enq_shrinks(c, x, ji == n_inner - 1, SolveRecord{}, solve == 0);
+        rc = enq_shrinks(c, x, ji == n_inner - 1, solve);
         if (rc) return rc;
         q_valid = true;  // the shrinks left A x = b - r in q
       }

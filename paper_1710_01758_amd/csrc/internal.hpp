@@ -100,9 +100,7 @@ struct WaveArgs {
   float2* coef;
   float2* bw;
   float2* uw;
-  const float2* g;
-  const float2* ux;
-  const float2* uy;
+  const float2* tvr;  // synthesis, mode 1: g + lam (D_x^H u_x + D_y^H u_y), from the level-0 analysis
   float2* rhs;
 };
 
@@ -132,14 +130,21 @@ struct OuterArgs {
   SolveRecord rec;
 };
 
+// Fused TV shrink/update of the level-0 analysis.  It leaves the TV part of
+// the next right-hand side, tvr = g + lam (D_x^H u_x + D_y^H u_y) (g after the
+// outer update), instead of u_x and u_y.
+// The Bregman variables b_x, b_y are read from bxi, byi and written to bx, by
+// (two buffers used in turn: a workgroup reads the old b on its neighbours'
+// pixels, which they overwrite in the same launch).
 struct TvArgs {
   int enabled;
+  const float2* bxi;
+  const float2* byi;
   float2* bx;
   float2* by;
-  float2* ux;
-  float2* uy;
+  float2* tvr;
   OuterArgs outer;
-  int fresh;  // bx, by start at zero (not read)
+  int fresh;  // b_x, b_y start at zero (not read)
 };
 
 struct Simple {
@@ -214,7 +219,7 @@ void fill_twiddles(float2* tw_host);
 // ---- per-pixel kernels (k_sb.hip)
 hipError_t launch_pcg_check(hipStream_t st, const Ws& w, int nslices, double tol, int setup, float2* x);
 hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, int fresh, const OuterArgs& oa,
-                            const float2* x,
+                            const float2* x, const float2* bxi, const float2* byi,
                             float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw);
 hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, const float2* ux, const float2* uy,
                                 const float2* uw, float2* rhs);

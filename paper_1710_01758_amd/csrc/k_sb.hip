@@ -94,14 +94,16 @@ __global__ void k_set_int(int* p, int v) {
 // update (Algorithm 1 steps 13-15, image-domain form)
 //   A_data x = A x - lam (D_x^H D_x + D_y^H D_y) x - gam x
 // need no further operator application.  lap = 4 x - (four neighbours).
-__device__ __forceinline__ void outer_at(const SliceDev& sd, const OuterArgs& oa, long long pp, float2 xc,
-                                         float2 lap, float2 bv, float2 rv, float2 gv, float2 g1v) {
+__device__ __forceinline__ float2 outer_at(const SliceDev& sd, const OuterArgs& oa, long long pp, float2 xc,
+                                           float2 lap, float2 bv, float2 rv, float2 gv, float2 g1v) {
   const float2 ax = csub(bv, rv);
   oa.q[pp] = ax;
   if (oa.mode == 2) {
     const float2 ad = make_float2(ax.x - sd.lam * lap.x - sd.gam * xc.x, ax.y - sd.lam * lap.y - sd.gam * xc.y);
-    oa.g[pp] = make_float2(gv.x + g1v.x - ad.x, gv.y + g1v.y - ad.y);
+    gv = make_float2(gv.x + g1v.x - ad.x, gv.y + g1v.y - ad.y);
+    oa.g[pp] = gv;
   }
+  return gv;  // g after the step
 }
 
 // ------------------------------------------------------- TV shrink/update
@@ -110,7 +112,8 @@ __device__ __forceinline__ void outer_at(const SliceDev& sd, const OuterArgs& oa
 // right-hand side uses D^H u).  With no wavelet the same is done on x itself
 // with threshold 1/gam.
 __global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, int fresh, OuterArgs oa,
-                                                   const float2* __restrict__ x,
+                                                   const float2* __restrict__ x, const float2* __restrict__ bxi,
+                                                   const float2* __restrict__ byi,
                                                    float2* __restrict__ bx, float2* __restrict__ by,
                                                    float2* __restrict__ ux, float2* __restrict__ uy,
                                                    float2* __restrict__ bw, float2* __restrict__ uw) {
@@ -137,14 +140,14 @@ __global__ __launch_bounds__(256) void k_tv_shrink(Ws w, int only_nowavelet, int
     }
     const float2 zero = make_float2(0.f, 0.f);
     {
-      const float2 v = cadd(csub(xc, xu), fresh ? zero : bx[o + p]);
+      const float2 v = cadd(csub(xc, xu), fresh ? zero : bxi[o + p]);
       const float2 d = shrink(v, tl);
       const float2 b = csub(v, d);
       bx[o + p] = b;
       ux[o + p] = csub(d, b);
     }
     {
-      const float2 v = cadd(csub(xc, xl), fresh ? zero : by[o + p]);
+      const float2 v = cadd(csub(xc, xl), fresh ? zero : byi[o + p]);
       const float2 d = shrink(v, tl);
       const float2 b = csub(v, d);
       by[o + p] = b;
@@ -176,6 +179,7 @@ __global__ __launch_bounds__(256) void k_rhs_nowavelet(Ws w, const float2* __res
                                                        const float2* __restrict__ uw, float2* __restrict__ rhs) {
   const int s = blockIdx.y;
   const SliceDev sd = w.sl[s];
+  if (sd.levels > 0 && sd.wavelet != 0) return;  // the wavelet synthesis writes these
   const long long np = (long long)sd.m * sd.n;
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += (long long)gridDim.x * blockDim.x) {
     const int i = int(p / sd.n), j = int(p % sd.n);
@@ -245,7 +249,8 @@ __device__ __forceinline__ int wrap(int i, int L, bool small) {
 
 template <int K>
 __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs& a, const TvArgs& tv,
-                                             float2 (*tile)[kWIn + 1], float2 (*rowb)[2 * kWT + 1], int bt) {
+                                             float2 (*tile)[kWIn + 1], float2 (*rowb)[2 * kWT + 1],
+                                             float2 (*uys)[2 * kWT + 1], int bt) {
   const int n = sd.n;
   const int ml = sd.m >> a.level, nl = n >> a.level;
   const int mh = ml / 2, nh = nl / 2;
@@ -275,31 +280,36 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
       }
     }
   }
+  // Level 0 covers whole 2 kWT x 2 kWT pixel blocks (image sides are
+  // multiples of 32); the TV step also needs b_x on the row below the block
+  // and b_y on the column to its right (threads 0 .. 4 kWT - 1, one each).
   constexpr int PER_TV = 4 * kWT * kWT / kWThreads;
   const OuterArgs& oa = tv.outer;
   const bool tv_here = tv.enabled && a.level == 0;
   float2 bxs[PER_TV] = {}, bys[PER_TV] = {}, obs[PER_TV], ors[PER_TV], ogs[PER_TV] = {}, og1s[PER_TV] = {};
+  float2 bhalo = make_float2(0.f, 0.f);
   if (tv_here) {
 #pragma unroll
     for (int e = 0; e < PER_TV; ++e) {
       const int idx = threadIdx.x + kWThreads * e;
       const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
-      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
-      if (i < ml && jj < nl) {
-        const long long pp = o + (long long)i * n + jj;
-        if (!tv.fresh) {
-          bxs[e] = tv.bx[pp];
-          bys[e] = tv.by[pp];
-        }
-        if (oa.mode) {
-          obs[e] = oa.b[pp];
-          ors[e] = oa.r[pp];
-          if (oa.mode == 2) {
-            ogs[e] = oa.g[pp];
-            og1s[e] = oa.g1[pp];
-          }
-        }
+      const long long pp = o + (long long)(2 * k0 + ia) * n + 2 * c0 + jb;
+      if (!tv.fresh) {
+        bxs[e] = tv.bxi[pp];
+        bys[e] = tv.byi[pp];
       }
+      ogs[e] = oa.g[pp];
+      if (oa.mode) {
+        obs[e] = oa.b[pp];
+        ors[e] = oa.r[pp];
+        if (oa.mode == 2) og1s[e] = oa.g1[pp];
+      }
+    }
+    if (!tv.fresh && threadIdx.x < 4 * kWT) {
+      const int t = threadIdx.x;
+      const int id = (2 * k0 + 2 * kWT) % ml, jr = (2 * c0 + 2 * kWT) % nl;
+      bhalo = t < 2 * kWT ? tv.bxi[o + (long long)id * n + 2 * c0 + t]
+                          : tv.byi[o + (long long)(2 * k0 + t - 2 * kWT) * n + jr];
     }
   }
   {
@@ -356,38 +366,64 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
     else coef_out(sd, a, plo, lo, blo[e]);
     coef_out(sd, a, phi, hi, bhi[e]);
   }
-  // level 0: Algorithm 1 steps 6, 7, 9, 10 on the 2 kWT x 2 kWT pixel block
-  if (tv.enabled && a.level == 0) {
+  // level 0: Algorithm 1 steps 6, 7, 9, 10 on the 2 kWT x 2 kWT pixel block,
+  // the outer update (steps 13-15), and the TV part of the next right-hand
+  // side (step 4): tvr = g + lam (D_x^H u_x + D_y^H u_y), with u_x on the row
+  // below the block and u_y on the column to its right recomputed here
+  if (tv_here) {
+    __syncthreads();  // rowb is reused for u_x once the axis-0 pass has read it
+    float2 (*uxs)[2 * kWT + 1] = rowb;
     const float thr = 1.0f / sd.lam;
-    constexpr int PER = PER_TV;
+    float2 gs[PER_TV];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
+    for (int e = 0; e < PER_TV; ++e) {
       const int idx = threadIdx.x + kWThreads * e;
       const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
-      const int i = 2 * k0 + ia, jj = 2 * c0 + jb;
-      if (i >= ml || jj >= nl) continue;
-      const long long pp = o + (long long)i * n + jj;
+      const long long pp = o + (long long)(2 * k0 + ia) * n + 2 * c0 + jb;
       const float2 xc = tile[1 + ia][1 + jb], xu = tile[ia][1 + jb], xl = tile[1 + ia][jb];
-      const float2 bxv = bxs[e], byv = bys[e];
+      gs[e] = ogs[e];
       if (oa.mode) {
         const float2 xd = tile[2 + ia][1 + jb], xr = tile[1 + ia][2 + jb];
         const float2 lap = make_float2(4.f * xc.x - xu.x - xd.x - xl.x - xr.x, 4.f * xc.y - xu.y - xd.y - xl.y - xr.y);
-        outer_at(sd, oa, pp, xc, lap, obs[e], ors[e], ogs[e], og1s[e]);
+        gs[e] = outer_at(sd, oa, pp, xc, lap, obs[e], ors[e], ogs[e], og1s[e]);
       }
       {
-        const float2 v = cadd(csub(xc, xu), bxv);
+        const float2 v = cadd(csub(xc, xu), bxs[e]);
         const float2 d = shrink(v, thr);
         const float2 b = csub(v, d);
         tv.bx[pp] = b;
-        tv.ux[pp] = csub(d, b);
+        uxs[ia][jb] = csub(d, b);
       }
       {
-        const float2 v = cadd(csub(xc, xl), byv);
+        const float2 v = cadd(csub(xc, xl), bys[e]);
         const float2 d = shrink(v, thr);
         const float2 b = csub(v, d);
         tv.by[pp] = b;
-        tv.uy[pp] = csub(d, b);
+        uys[ia][jb] = csub(d, b);
       }
+    }
+    if (threadIdx.x < 4 * kWT) {
+      const int t = threadIdx.x;
+      if (t < 2 * kWT) {  // u_x on the row below the block
+        const float2 v = cadd(csub(tile[1 + 2 * kWT][1 + t], tile[2 * kWT][1 + t]), bhalo);
+        const float2 d = shrink(v, thr);
+        uxs[2 * kWT][t] = csub(d, csub(v, d));
+      } else {  // u_y on the column to the right
+        const int ia = t - 2 * kWT;
+        const float2 v = cadd(csub(tile[1 + ia][1 + 2 * kWT], tile[1 + ia][2 * kWT]), bhalo);
+        const float2 d = shrink(v, thr);
+        uys[ia][2 * kWT] = csub(d, csub(v, d));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER_TV; ++e) {
+      const int idx = threadIdx.x + kWThreads * e;
+      const int ia = idx / (2 * kWT), jb = idx % (2 * kWT);
+      const long long pp = o + (long long)(2 * k0 + ia) * n + 2 * c0 + jb;
+      const float2 x0 = uxs[ia][jb], x1 = uxs[ia + 1][jb], y0 = uys[ia][jb], y1 = uys[ia][jb + 1];
+      tv.tvr[pp] = make_float2(gs[e].x + sd.lam * ((x0.x - x1.x) + (y0.x - y1.x)),
+                               gs[e].y + sd.lam * ((x0.y - x1.y) + (y0.y - y1.y)));
     }
   }
 }
@@ -395,14 +431,15 @@ __device__ __forceinline__ void dwt_ana_tile(const SliceDev& sd, const WaveArgs&
 __global__ __launch_bounds__(256) void k_dwt_ana(Ws w, WaveArgs a, TvArgs tv) {
   __shared__ float2 tile[kWIn][kWIn + 1];
   __shared__ float2 rowb[kWIn][2 * kWT + 1];
+  __shared__ float2 uys[2 * kWT][2 * kWT + 1];
   if (tv.outer.rec.counter && blockIdx.x == 0 && blockIdx.y == 0) record_solve(w, tv.outer.rec);
   const SliceDev sd = w.sl[blockIdx.y];
   if (sd.wavelet == 0 || a.level >= sd.levels) return;
   const int mh = (sd.m >> a.level) / 2, nh = (sd.n >> a.level) / 2;
   const int bt = xcd_tile(blockIdx.x, gridDim.x);
   if (bt >= ((nh + kWT - 1) / kWT) * ((mh + kWT - 1) / kWT)) return;
-  if (sd.wavelet == 1) dwt_ana_tile<2>(sd, a, tv, tile, rowb, bt);
-  else dwt_ana_tile<8>(sd, a, tv, tile, rowb, bt);
+  if (sd.wavelet == 1) dwt_ana_tile<2>(sd, a, tv, tile, rowb, uys, bt);
+  else dwt_ana_tile<8>(sd, a, tv, tile, rowb, uys, bt);
 }
 
 // Synthesis of one level: a 2 kWT x 2 kWT output pixel block from the four
@@ -426,27 +463,18 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
   const Filt<K> f;
   // pixel pairs (columns 2b, 2b + 1 of the block) per thread in the last pass
   constexpr int PP = 2 * kWT * kWT / kWThreads;
-  // the right-hand side's operands (level 0, mode 1) are requested first so
-  // that they are in flight during the band loads and both filter passes;
-  // the workspace images are 16-byte aligned and a pair never wraps
+  // the right-hand side's TV part (level 0, mode 1) is requested first so
+  // that it is in flight during the band loads and both filter passes; the
+  // workspace images are 16-byte aligned
   const bool rhs_mode = a.level == 0 && a.mode == 1;
-  float4 rg[PP], rx0[PP], rx1[PP], ry0[PP];
-  float2 ry2[PP];
+  float4 rt[PP];
   if (rhs_mode) {
 #pragma unroll
     for (int e = 0; e < PP; ++e) {
       const int pidx = threadIdx.x + kWThreads * e;
       const int ia = pidx / kWT, b = pidx % kWT;
       const int i = 2 * k0 + ia, jj = 2 * c0 + 2 * b;
-      if (i < ml && jj < nl) {
-        const long long p = o + (long long)i * n + jj;
-        const int id = i + 1 == sd.m ? 0 : i + 1, jr = jj + 2 == n ? 0 : jj + 2;
-        rg[e] = *reinterpret_cast<const float4*>(a.g + p);
-        rx0[e] = *reinterpret_cast<const float4*>(a.ux + p);
-        rx1[e] = *reinterpret_cast<const float4*>(a.ux + o + (long long)id * n + jj);
-        ry0[e] = *reinterpret_cast<const float4*>(a.uy + p);
-        ry2[e] = a.uy[o + (long long)i * n + jr];
-      }
+      if (i < ml && jj < nl) rt[e] = *reinterpret_cast<const float4*>(a.tvr + o + (long long)i * n + jj);
     }
   }
   {
@@ -506,16 +534,11 @@ __device__ __forceinline__ void dwt_syn_tile(const SliceDev& sd, const WaveArgs&
     }
     const long long p = o + (long long)i * n + jj;
     if (rhs_mode) {
-      // Algorithm 1 step 4: g + lam (D_x^H u_x + D_y^H u_y) + gam W^H u_w
-      const float4 g4 = rg[e], x0 = rx0[e], x1 = rx1[e], y0 = ry0[e];
-      const float2 y2 = ry2[e];
-      const float lam = sd.lam, gam = sd.gam;
-      float4 out;
-      out.x = g4.x + lam * ((x0.x - x1.x) + (y0.x - y0.z)) + gam * ev.x;
-      out.y = g4.y + lam * ((x0.y - x1.y) + (y0.y - y0.w)) + gam * ev.y;
-      out.z = g4.z + lam * ((x0.z - x1.z) + (y0.z - y2.x)) + gam * od.x;
-      out.w = g4.w + lam * ((x0.w - x1.w) + (y0.w - y2.y)) + gam * od.y;
-      *reinterpret_cast<float4*>(a.rhs + p) = out;
+      // Algorithm 1 step 4: [g + lam (D_x^H u_x + D_y^H u_y)] + gam W^H u_w
+      const float gam = sd.gam;
+      const float4 t = rt[e];
+      *reinterpret_cast<float4*>(a.rhs + p) =
+          make_float4(t.x + gam * ev.x, t.y + gam * ev.y, t.z + gam * od.x, t.w + gam * od.y);
     } else {
       a.out[p] = ev;
       a.out[p + 1] = od;
@@ -640,9 +663,10 @@ hipError_t launch_set_int(hipStream_t st, int* p, int v) {
 }
 
 hipError_t launch_tv_shrink(const Simple& S, const Ws& w, int only_nowavelet, int fresh, const OuterArgs& oa,
-                            const float2* x, float2* bx, float2* by, float2* ux, float2* uy, float2* bw, float2* uw) {
-  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, only_nowavelet, fresh, oa, x, bx, by,
-                     ux, uy, bw, uw);
+                            const float2* x, const float2* bxi, const float2* byi, float2* bx, float2* by, float2* ux,
+                            float2* uy, float2* bw, float2* uw) {
+  hipLaunchKernelGGL(k_tv_shrink, simple_grid(S), dim3(256), 0, S.stream, w, only_nowavelet, fresh, oa, x, bxi, byi,
+                     bx, by, ux, uy, bw, uw);
   return hipGetLastError();
 }
 

@@ -485,3 +485,33 @@ def test_parameter_sets_iteration_counts_match_oracle(torch, B):
         gains[sid] = sum(got["none"]) / sum(got["circulant"])
         ctx.close()
     assert gains[2] < gains[1] and gains[2] < gains[3], gains
+
+
+def test_split_bregman_batch_matches_single_slices(torch, B):
+    """Slices of a batch reconstruct exactly as they do alone (no coil split,
+    same kernels and reduction order), and a batch run is reproducible: a
+    race between the workgroups of one launch (e.g. a tile reading its
+    neighbours' Bregman variables while they are rewritten) shows up as a
+    slice that differs from its stand-alone reconstruction or from run to run."""
+    _say("sb batch of 24 vs single slices")
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1e3)
+    insts = [_inst(spec, gen.eval_seed(2, i)) for i in range(24)]
+    ctx, ksp = _ctx(B, insts)
+    ctx.set_option(B.OPT_COIL_GROUPS, 1)
+    ctx.build_preconditioner("circulant")
+    runs = []
+    for _ in range(2):
+        x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+        it_b, rc = ctx.split_bregman_recon(ksp, x, n_outer=12, tol=1e-3, maxit=1000)
+        runs.append(_host(x).reshape(24, spec.m, spec.n))
+    assert np.array_equal(runs[0], runs[1])
+    for s in (0, 13, 23):
+        c1, k1 = _ctx(B, [insts[s]])
+        c1.set_option(B.OPT_COIL_GROUPS, 1)
+        c1.build_preconditioner("circulant")
+        x1 = torch.zeros(c1.image_elems, dtype=torch.complex64, device="cuda")
+        it1, rc = c1.split_bregman_recon(k1, x1, n_outer=12, tol=1e-3, maxit=1000)
+        assert np.array_equal(it1[:, 0], it_b[:, s]), (s, it1[:, 0], it_b[:, s])
+        err = H.rel_err(_host(x1).reshape(spec.m, spec.n), runs[0][s])
+        _say(f"  slice {s}: rel diff batch vs alone {err:.2e}")
+        assert err < 1e-6, (s, err)
