@@ -36,7 +36,7 @@ struct SliceDev {
   long long img;   // element offset of the slice in packed image-shaped buffers
   long long coil;  // element offset in packed coil-shaped buffers [nc][m][n]
   long long mask;  // byte offset in the packed mask buffer
-  long long aux;   // offset of the slice's (n / 16) x m FP64 coil-power partials
+  long long aux;   // offset of the slice's (n / col_tile(m)) x m FP64 coil-power partials
 };
 
 // Per-slice PCG control block; lives in device memory.
@@ -227,7 +227,7 @@ hipError_t launch_rhs_nowavelet(const Simple& S, const Ws& w, const float2* g, c
 // slices of the level's 16 x 16 coefficient tiles
 hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a, const TvArgs& tv, int tiles);
 int wavelet_tiles(int m, int n, int level);
-hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, const float* corr, float* kraw,
+hipError_t launch_build_k(const Simple& S, const Ws& w, double* pbar, const float* corr, float* kraw,
                           float* kinv, float* jac, int* bad);
 hipError_t launch_fill(hipStream_t st, float2* p, long long count, float2 v);
 hipError_t launch_add_gamma(const Simple& S, const Ws& w, const float2* wx, const float2* x, float2* y);

@@ -563,29 +563,28 @@ __global__ __launch_bounds__(256) void k_dwt_syn(Ws w, WaveArgs a) {
 // for a line mask, k_c(u) = (1/N^2) sum_l r(l) Pbar(l - u); optional
 // multiplicative correction; outputs k, 1 / (k m n) and the Jacobi inverse
 // diagonal 1 / (mu |Omega|/N sum_c |S_c|^2 + 4 lam + gam).
-__global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict__ pbar, const float* __restrict__ corr,
-                                                 float* __restrict__ kraw, float* __restrict__ kinv,
-                                                 float* __restrict__ jac, int* __restrict__ bad) {
+// One workgroup per slice: k_c along the lines and the row part of k,
+//   krow(u) = mu k_c(u) + lam (2 - 2 cos(2 pi u / m)) + gam,
+// and the sampled fraction |Omega| / m, written over the slice's Pbar
+// partials (krow at [0, m), the fraction at m) once they are summed.
+__global__ __launch_bounds__(256) void k_build_krow(Ws w, double* __restrict__ pbar) {
   __shared__ double sp[1024];
-  __shared__ double skc[1024];
-  __shared__ double sdv[1024];
   __shared__ int smk[1024];
   __shared__ int ssum;
-  const int s = blockIdx.y;
+  const int s = blockIdx.x;
   const SliceDev sd = w.sl[s];
   if (sd.mask_kind != 0) return;  // 2D masks: k_build_k2d
   const int m = sd.m, n = sd.n;
   const int ntile = n / col_tile(m);
   const uint8_t* mk = w.mask + sd.mask;
-  // this workgroup's rows (the grid has at most m workgroups per slice)
-  const int u0 = (int)((long long)blockIdx.x * m / gridDim.x), u1 = (int)((long long)(blockIdx.x + 1) * m / gridDim.x);
+  double* pb = pbar + sd.aux;
   if (threadIdx.x == 0) ssum = 0;
   __syncthreads();
   int cnt = 0;
   for (int u = threadIdx.x; u < m; u += blockDim.x) {
     double a = 0.0;
 #pragma unroll 16
-    for (int tl = 0; tl < ntile; ++tl) a += pbar[sd.aux + (long long)tl * m + u];
+    for (int tl = 0; tl < ntile; ++tl) a += pb[(long long)tl * m + u];
     sp[u] = a * n;
     smk[u] = mk[u] ? 1 : 0;
     cnt += mk[u] ? 1 : 0;
@@ -593,10 +592,7 @@ __global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict_
   atomicAdd(&ssum, cnt);
   __syncthreads();
   const double N = (double)m * n;
-  // k_c(u) of this workgroup's rows from the sampled lines, plus the row part
-  // of k_d (2 - 2 cos(2 pi u / m)) and gam; the column part of k_d
-  // (2 - 2 cos(2 pi v / n)) as a table
-  for (int u = u0 + (int)threadIdx.x; u < u1; u += blockDim.x) {
+  for (int u = threadIdx.x; u < m; u += blockDim.x) {
     double a = 0.0;
 #pragma unroll 16
     for (int l = 0; l < m; ++l) {
@@ -604,17 +600,32 @@ __global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict_
       const double pv = sp[d < 0 ? d + m : d];
       if (smk[l]) a += pv;
     }
-    skc[u - u0] = (double)sd.mu * (a / (N * N)) + (double)sd.lam * (2.0 - 2.0 * cospi(2.0 * u / m)) + (double)sd.gam;
+    pb[u] = (double)sd.mu * (a / (N * N)) + (double)sd.lam * (2.0 - 2.0 * cospi(2.0 * u / m)) + (double)sd.gam;
   }
+  if (threadIdx.x == 0) pb[m] = (double)ssum / m;
+}
+
+// k(u, v) = krow(u) + lam (2 - 2 cos(2 pi v / n)), a row band per workgroup.
+__global__ __launch_bounds__(256) void k_build_k(Ws w, const double* __restrict__ pbar, const float* __restrict__ corr,
+                                                 float* __restrict__ kraw, float* __restrict__ kinv,
+                                                 float* __restrict__ jac, int* __restrict__ bad) {
+  __shared__ double sdv[1024];
+  const int s = blockIdx.y;
+  const SliceDev sd = w.sl[s];
+  if (sd.mask_kind != 0) return;
+  const int m = sd.m, n = sd.n;
+  const double* pb = pbar + sd.aux;
+  const int u0 = (int)((long long)blockIdx.x * m / gridDim.x), u1 = (int)((long long)(blockIdx.x + 1) * m / gridDim.x);
   for (int v = threadIdx.x; v < n; v += blockDim.x) sdv[v] = (double)sd.lam * (2.0 - 2.0 * cospi(2.0 * v / n));
   __syncthreads();
-  const double frac = (double)ssum / m;
+  const double N = (double)m * n;
+  const double frac = pb[m];
   const long long np = (long long)(u1 - u0) * n;
   int badl = 0;
   for (long long q = threadIdx.x; q < np; q += blockDim.x) {
     const int du = int(q / n), v = int(q - (long long)du * n);
     const long long p = (long long)(u0 + du) * n + v;
-    double k = skc[du] + sdv[v];
+    double k = pb[u0 + du] + sdv[v];
     if (corr) k *= (double)corr[sd.img + p];
     if (!(k > 0.0) || !isfinite(k)) badl = 1;
     kraw[sd.img + p] = (float)k;
@@ -690,8 +701,9 @@ hipError_t launch_wavelet(const Simple& S, const Ws& w, const WaveArgs& a, const
   return hipGetLastError();
 }
 
-hipError_t launch_build_k(const Simple& S, const Ws& w, const double* pbar, const float* corr, float* kraw,
+hipError_t launch_build_k(const Simple& S, const Ws& w, double* pbar, const float* corr, float* kraw,
                           float* kinv, float* jac, int* bad) {
+  hipLaunchKernelGGL(k_build_krow, dim3(S.nslices), dim3(256), 0, S.stream, w, pbar);
   dim3 grid = simple_grid(S);
   if (grid.x > 64) grid.x = 64;
   hipLaunchKernelGGL(k_build_k, grid, dim3(256), 0, S.stream, w, pbar, corr, kraw, kinv, jac, bad);
