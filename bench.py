@@ -81,14 +81,16 @@ def run_apply_mode(torch, ctx, insts):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_hbm_traffic.md")
+VALU_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_valu.md")
+SIMDS, PEAK_CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs; a wave64 FP32 VALU op issues in 4 cycles
 
 
-def measured_traffic():
-    """HBM bytes per apply_A launch from the committed counter summary, or None
-    if the kernel sources changed since the counters were taken."""
+def profile_fields(path):
+    """The `key: value` lines of a committed counter summary, or None if the
+    kernel sources changed since the counters were taken."""
     import hashlib
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(path).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in txt.splitlines() if ": " in line and not line.startswith(("|", "#")))
@@ -98,9 +100,35 @@ def measured_traffic():
             h.update(open(os.path.join(ROOT, f), "rb").read())
         if h.hexdigest() != fields["kernel_source_sha256"].strip():
             return None
-        return int(fields["traffic_bytes_per_launch"])
-    except (KeyError, OSError, ValueError):
+    except (KeyError, OSError):
         return None
+    return fields
+
+
+def measured_traffic():
+    """HBM bytes per apply_A launch from the committed counter summary, or None
+    if the kernel sources changed since the counters were taken."""
+    f = profile_fields(TRAFFIC_PROFILE)
+    try:
+        return int(f["traffic_bytes_per_launch"]) if f else None
+    except (KeyError, ValueError):
+        return None
+
+
+def valu_roofline(avg_s):
+    """The apply kernel against its vector-ALU issue bound: counted wave64 VALU
+    instructions per launch (committed counter summary) x 4 cycles over the
+    1024 SIMDs at the 2.4 GHz peak clock, against this run's launch time."""
+    f = profile_fields(VALU_PROFILE)
+    try:
+        instr = float(f["valu_wave_instr_per_launch"]) if f else None
+    except (KeyError, ValueError):
+        instr = None
+    if instr is None:
+        return None
+    floor = instr * 4 / (SIMDS * PEAK_CLOCK_HZ)
+    return {"bound": "alu", "valu_wave_instr_per_launch": int(instr), "floor_us_at_peak_clock": round(floor * 1e6, 2),
+            "frac": round(floor / avg_s, 4), "sustained_clock_GHz": float(f.get("sustained_clock_GHz", "nan"))}
 
 
 def cpu_baseline(inst, min_seconds=10.0):
@@ -481,7 +509,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": (f"k_col_apply<256, 0, 0> (fused apply_A, {a.batch} slices per launch)" if split[0] == 1
                                 else f"k_col_apply<256, 0, 1> + <256, 0, 2> (apply_A, coil split {split[0]})"),
-                     "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": bytes_apply},
+                     "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": bytes_apply,
+                     "valu": valu_roofline(t_apply) if split[0] == 1 else None},
     }
     if not a.no_extra:
         log("bench: 512x512x32 slice")
