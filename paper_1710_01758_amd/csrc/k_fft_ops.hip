@@ -28,7 +28,7 @@ namespace pics {
 //              and the mode's outputs (CA_PCG reads p back from pn)
 // ----------------------------------------------------------------------------
 template <int M, int MODE, int PH>
-__global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
+__global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void k_col_apply(
     Ws w, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
     const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, int ngroups,
     float2* __restrict__ dpart, long long dstride) {
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
       }
     }
   };
-  constexpr bool LATE_HALO = HP > 4;
+  constexpr bool LATE_HALO = HP > 4 || M == 320;  // (320: registers, see the coil loop)
   if (MODE != CA_PCG || PH == AP_FIN) {
 #pragma unroll
     for (int e = 0; e < E; ++e) pv[e] = xs[(t + NT * e) * n + col];
@@ -160,9 +160,10 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS) void k_col_apply(
     const float inv_m = 1.0f / M;
     const float2* __restrict__ S = w.sens + sd.coil + t * n + col;
     const int plane = M * n;
-    // the next coil's maps are prefetched except at length 1024, where the
-    // extra registers would spill
-    constexpr bool PREFETCH = M < 1024;
+    // the next coil's maps are prefetched, except at length 1024, where the
+    // extra registers would spill, and at 320, where the registers they free
+    // (with the halo loaded late) give two waves per SIMD instead of one
+    constexpr bool PREFETCH = M < 1024 && M != 320;
     float2 sv[E], sn[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) sv[e] = S[(long long)c0 * plane + NT * e * n];

@@ -23,7 +23,10 @@ struct ColCfg {
 // exchange its own LDS buffer (two buffers used in turn, so a barrier after
 // reading an exchange is not needed).
 template <int M>
-using ApplyCfg = ColCfg<M>;
+struct ApplyCfg : ColCfg<M> {
+  // workgroups per CU the register allocation must allow (2 waves per SIMD)
+  static constexpr int MIN_BLOCKS = M == 320 ? 2 : 1;
+};
 template <int M>
 struct ApplyDual { static constexpr bool value = M <= 256; };
 template <int N>
