@@ -161,9 +161,10 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
     const float2* __restrict__ S = w.sens + sd.coil + t * n + col;
     const int plane = M * n;
     // the next coil's maps are prefetched, except at length 1024, where the
-    // extra registers would spill, and at 320, where the registers they free
-    // (with the halo loaded late) give two waves per SIMD instead of one
-    constexpr bool PREFETCH = M < 1024 && M != 320;
+    // extra registers would spill, and at 320 and 512, where the registers
+    // they free (at 320 with the halo loaded late) give two waves per SIMD
+    // instead of one
+    constexpr bool PREFETCH = M < 1024 && M != 320 && M != 512;
     float2 sv[E], sn[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) sv[e] = S[(long long)c0 * plane + NT * e * n];

@@ -24,8 +24,9 @@ struct ColCfg {
 // reading an exchange is not needed).
 template <int M>
 struct ApplyCfg : ColCfg<M> {
-  // workgroups per CU the register allocation must allow (2 waves per SIMD)
-  static constexpr int MIN_BLOCKS = M == 320 ? 2 : 1;
+  // workgroups per CU the register allocation must allow: two waves per
+  // SIMD at 320 (4-wave workgroups) and 512 (2-wave workgroups)
+  static constexpr int MIN_BLOCKS = M == 320 ? 2 : M == 512 ? 4 : 1;
 };
 template <int M>
 struct ApplyDual { static constexpr bool value = M <= 256; };
