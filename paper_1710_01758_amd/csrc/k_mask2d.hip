@@ -75,15 +75,39 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_sp(Ws w, int pk, dou
 #pragma unroll
     for (int e = 0; e < E; ++e) pn[row + t + NT * e] = pv[e];
   }
+  // the next coil's maps are loaded while this coil is transformed (not at
+  // length 1024: 1024-thread workgroups leave no registers for them)
   const long long plane = (long long)sd.m * N;
-  for (int c = 0; c < sd.nc; ++c) {
-    const long long crow = sd.coil + c * plane + (long long)i * N;
-    float2 v[E];
+  const long long row0 = sd.coil + (long long)i * N + t;
+  if constexpr (N < 1024) {
+    float2 sv[E], sn[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = cmul(w.sens[crow + t + NT * e], pv[e]);
-    fft<N, -1, RowLay<N>>(v, t, lds, rr_, s_tw);
+    for (int e = 0; e < E; ++e) sv[e] = w.sens[row0 + NT * e];
+    for (int c = 0; c < sd.nc; ++c) {
+      const long long crow = row0 + c * plane;
+      if (c + 1 < sd.nc) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) coil[crow + t + NT * e] = v[e];
+        for (int e = 0; e < E; ++e) sn[e] = w.sens[crow + plane + NT * e];
+      }
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cmul(sv[e], pv[e]);
+      fft<N, -1, RowLay<N>>(v, t, lds, rr_, s_tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) coil[crow + NT * e] = v[e];
+#pragma unroll
+      for (int e = 0; e < E; ++e) sv[e] = sn[e];
+    }
+  } else {
+    for (int c = 0; c < sd.nc; ++c) {
+      const long long crow = row0 + c * plane;
+      float2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cmul(w.sens[crow + NT * e], pv[e]);
+      fft<N, -1, RowLay<N>>(v, t, lds, rr_, s_tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) coil[crow + NT * e] = v[e];
+    }
   }
 }
 
@@ -106,12 +130,21 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_mask2d(Ws w, int use
   float sc[E];  // r(u, col) / N: the unitary pair's scale folded into the mask
 #pragma unroll
   for (int e = 0; e < E; ++e) sc[e] = mk[(long long)(t + NT * e) * n + col] ? inv_n : 0.f;
+  // the next coil's column is loaded while this coil is transformed
   const long long plane = (long long)M * n;
+  float2 v[E], vn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = coil[sd.coil + col + (long long)(t + NT * e) * n];
   for (int c = 0; c < sd.nc; ++c) {
     float2* cb = coil + sd.coil + c * plane + col;
-    float2 v[E];
+    if (c > 0) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = cb[(long long)(t + NT * e) * n];
+      for (int e = 0; e < E; ++e) v[e] = vn[e];
+    }
+    if (c + 1 < sd.nc) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) vn[e] = cb[plane + (long long)(t + NT * e) * n];
+    }
     fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cscale(v[e], sc[e]);
@@ -156,15 +189,45 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_acc(Ws w, int terms,
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
   if (terms & TERM_DATA) {
+    // the coil's maps are requested with its row, the next coil's row and
+    // maps while it is transformed (not at length 1024: no registers left)
     const long long plane = (long long)m * N;
-    for (int c = 0; c < sd.nc; ++c) {
-      const long long crow = sd.coil + c * plane + (long long)i * N;
-      float2 v[E];
+    const long long row0 = sd.coil + (long long)i * N + t;
+    if constexpr (N < 1024) {
+      float2 v[E], sv[E], vn[E], sn[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = coil[crow + t + NT * e];
-      fft<N, +1, RowLay<N>>(v, t, lds, rr_, s_tw);
+      for (int e = 0; e < E; ++e) {
+        v[e] = coil[row0 + NT * e];
+        sv[e] = w.sens[row0 + NT * e];
+      }
+      for (int c = 0; c < sd.nc; ++c) {
+        const long long crow = row0 + c * plane;
+        if (c + 1 < sd.nc) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(w.sens[crow + t + NT * e], v[e]));
+          for (int e = 0; e < E; ++e) {
+            vn[e] = coil[crow + plane + NT * e];
+            sn[e] = w.sens[crow + plane + NT * e];
+          }
+        }
+        fft<N, +1, RowLay<N>>(v, t, lds, rr_, s_tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(sv[e], v[e]));
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          v[e] = vn[e];
+          sv[e] = sn[e];
+        }
+      }
+    } else {
+      for (int c = 0; c < sd.nc; ++c) {
+        const long long crow = row0 + c * plane;
+        float2 v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = coil[crow + NT * e];
+        fft<N, +1, RowLay<N>>(v, t, lds, rr_, s_tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(w.sens[crow + NT * e], v[e]));
+      }
     }
     __syncthreads();  // the transforms are done with the LDS buffer
   }
