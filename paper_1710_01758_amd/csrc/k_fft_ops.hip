@@ -6,6 +6,8 @@
 // m rows; thread (t, j) holds rows t + NT e of column j (cyclic layout), so a
 // length-m transform along axis 0 runs in registers + LDS.  Row tiles: a
 // workgroup owns 16 rows, thread (t, r) holds columns t + NT e of row r.
+#include <type_traits>
+
 #include "tiles.hpp"
 
 namespace pics {
@@ -165,23 +167,21 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
     // they free (at 320 with the halo loaded late) give two waves per SIMD
     // instead of one
     constexpr bool PREFETCH = M < 1024 && M != 320 && M != 512;
-    float2 sv[E], sn[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) sv[e] = S[(long long)c0 * plane + NT * e * n];
-    for (int c = c0; c < sd.nc; c += cstep) {
-      if (!PREFETCH && c != c0) {
-        const float2* __restrict__ Sc = S + (long long)c * plane;
-#pragma unroll
-        for (int e = 0; e < E; ++e) sv[e] = Sc[NT * e * n];
-      }
-      if (PREFETCH && c + cstep < sd.nc) {
-        const float2* __restrict__ Sn = S + (long long)(c + cstep) * plane;
-#pragma unroll
-        for (int e = 0; e < E; ++e) sn[e] = Sn[NT * e * n];
-      }
+    // one coil: S_c p -> FFT -> mask / m -> IFFT -> += conj(S_c) (.); `cur`
+    // holds S_c, and with PF `nxt` receives the maps of coil pf once S_c p is
+    // formed, so that the load runs during the transforms.  PF is a template
+    // argument: a conditional load would make the compiler wait for every
+    // load in flight before the first use of `cur`.
+    auto coil_step = [&](auto pf_tag, const float2(&cur)[E], float2(&nxt)[E], int pf) {
+      constexpr bool PF = decltype(pf_tag)::value;
       float2 v[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = cmul(sv[e], pv[e]);
+      for (int e = 0; e < E; ++e) v[e] = cmul(cur[e], pv[e]);
+      if constexpr (PF) {
+        const float2* __restrict__ Sn = S + (long long)pf * plane;
+#pragma unroll
+        for (int e = 0; e < E; ++e) nxt[e] = Sn[NT * e * n];
+      }
       if constexpr (DUAL) {
         // exchanges alternate between the two buffers across both transforms
         constexpr bool odd = (kExchanges<M> & 1) != 0;
@@ -196,10 +196,37 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
         fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
       }
 #pragma unroll
-      for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(sv[e], v[e]));
-      if (PREFETCH) {
+      for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(cur[e], v[e]));
+    };
+    const std::integral_constant<bool, true> with_prefetch;
+    const std::integral_constant<bool, false> without;
+    float2 sa[E], sb[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) sv[e] = sn[e];
+    for (int e = 0; e < E; ++e) sa[e] = S[(long long)c0 * plane + NT * e * n];
+    if constexpr (PREFETCH) {
+      // coils k = 0 .. K-1 of this workgroup (c0 + k cstep); two per trip,
+      // the map buffers swapping roles (no copies); the last one or two
+      // outside the loop, where nothing is left to prefetch
+      const int K = (sd.nc - c0 + cstep - 1) / cstep;
+      int k = 0;
+      for (; k + 2 < K; k += 2) {
+        coil_step(with_prefetch, sa, sb, c0 + (k + 1) * cstep);
+        coil_step(with_prefetch, sb, sa, c0 + (k + 2) * cstep);
+      }
+      if (k + 2 == K) {
+        coil_step(with_prefetch, sa, sb, c0 + (k + 1) * cstep);
+        coil_step(without, sb, sa, 0);
+      } else {
+        coil_step(without, sa, sb, 0);
+      }
+    } else {
+      for (int c = c0; c < sd.nc; c += cstep) {
+        if (c != c0) {
+          const float2* __restrict__ Sc = S + (long long)c * plane;
+#pragma unroll
+          for (int e = 0; e < E; ++e) sa[e] = Sc[NT * e * n];
+        }
+        coil_step(without, sa, sb, 0);
       }
     }
   }
