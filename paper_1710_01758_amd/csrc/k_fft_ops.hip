@@ -203,7 +203,11 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
     float2 sa[E], sb[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) sa[e] = S[(long long)c0 * plane + NT * e * n];
-    if constexpr (PREFETCH) {
+    // lengths up to 256 with 16 or fewer elements per thread: two coils per
+    // trip; the longer register files of 224 keep one coil per trip (four
+    // inlined transforms would spill)
+    constexpr bool PAIRS = PREFETCH && E <= 16;
+    if constexpr (PAIRS) {
       // coils k = 0 .. K-1 of this workgroup (c0 + k cstep); two per trip,
       // the map buffers swapping roles (no copies); the last one or two
       // outside the loop, where nothing is left to prefetch
@@ -221,12 +225,24 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
       }
     } else {
       for (int c = c0; c < sd.nc; c += cstep) {
-        if (c != c0) {
+        if (!PREFETCH && c != c0) {
           const float2* __restrict__ Sc = S + (long long)c * plane;
 #pragma unroll
           for (int e = 0; e < E; ++e) sa[e] = Sc[NT * e * n];
         }
+        if (PREFETCH) {
+          // unconditional (the last trip reloads its own maps): a
+          // conditional load makes the compiler wait on it before the
+          // transforms
+          const float2* __restrict__ Sn = S + (long long)(c + cstep < sd.nc ? c + cstep : c) * plane;
+#pragma unroll
+          for (int e = 0; e < E; ++e) sb[e] = Sn[NT * e * n];
+        }
         coil_step(without, sa, sb, 0);
+        if (PREFETCH) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) sa[e] = sb[e];
+        }
       }
     }
   }
@@ -514,7 +530,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_fft(Ws w, int ncoil_
   for (int c = 0; c < ncoil; ++c) {
     const long long rowbase = row0 + c * plane;
     if (!PF && c > 0) load_row(rowbase, v);
-    if (PF && c + 1 < ncoil) load_row(rowbase + plane, vn);
+    // (unconditional: the last trip reloads its own row, which keeps the
+    // compiler from waiting on the loads before the transform)
+    if (PF) load_row(rowbase + (c + 1 < ncoil ? plane : 0), vn);
     fft<N, DIR, RowLay<N>>(v, t, lds, rr_, s_tw);
     if (!dead_row) {
 #pragma unroll
@@ -597,10 +615,12 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_sb_init(Ws w, const 
     float2 sv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) sv[e] = w.sens[cb + off + (long long)NT * e * n];
-    if (c + 1 < sd.nc) {
+    {
+      // unconditional (the last trip reloads its own rows), see k_row_fft
+      const long long nx = c + 1 < sd.nc ? plane : 0;
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        vn[e] = ((live >> e) & 1u) ? coil_rows[cb + plane + off + (long long)NT * e * n] : make_float2(0.f, 0.f);
+        vn[e] = ((live >> e) & 1u) ? coil_rows[cb + nx + off + (long long)NT * e * n] : make_float2(0.f, 0.f);
     }
     fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
@@ -657,9 +677,11 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_power(Ws w, dou
 #pragma unroll
   for (int e = 0; e < E; ++e) sv[e] = S[(long long)NT * e * n];
   for (int c = 0; c < sd.nc; ++c) {
-    if (c + 1 < sd.nc) {
+    {
+      // unconditional (the last trip reloads its own maps), see k_row_fft
+      const int cn = c + 1 < sd.nc ? c + 1 : c;
 #pragma unroll
-      for (int e = 0; e < E; ++e) sn[e] = S[(c + 1) * plane + (long long)NT * e * n];
+      for (int e = 0; e < E; ++e) sn[e] = S[cn * plane + (long long)NT * e * n];
     }
     float2 v[E];
 #pragma unroll

@@ -85,9 +85,12 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_sp(Ws w, int pk, dou
     for (int e = 0; e < E; ++e) sv[e] = w.sens[row0 + NT * e];
     for (int c = 0; c < sd.nc; ++c) {
       const long long crow = row0 + c * plane;
-      if (c + 1 < sd.nc) {
+      {
+        // unconditional (the last trip reloads its own maps): a conditional
+        // load makes the compiler wait on it before the transform
+        const long long nx = c + 1 < sd.nc ? plane : 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) sn[e] = w.sens[crow + plane + NT * e];
+        for (int e = 0; e < E; ++e) sn[e] = w.sens[crow + nx + NT * e];
       }
       float2 v[E];
 #pragma unroll
@@ -141,9 +144,12 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_mask2d(Ws w, int use
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = vn[e];
     }
-    if (c + 1 < sd.nc) {
+    {
+      // unconditional (the last trip reloads its own column before writing
+      // it; the copy is not used)
+      const long long nx = c + 1 < sd.nc ? plane : 0;
 #pragma unroll
-      for (int e = 0; e < E; ++e) vn[e] = cb[plane + (long long)(t + NT * e) * n];
+      for (int e = 0; e < E; ++e) vn[e] = cb[nx + (long long)(t + NT * e) * n];
     }
     fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
 #pragma unroll
@@ -202,11 +208,13 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_acc(Ws w, int terms,
       }
       for (int c = 0; c < sd.nc; ++c) {
         const long long crow = row0 + c * plane;
-        if (c + 1 < sd.nc) {
+        {
+          // unconditional (the last trip reloads its own row and maps)
+          const long long nx = c + 1 < sd.nc ? plane : 0;
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            vn[e] = coil[crow + plane + NT * e];
-            sn[e] = w.sens[crow + plane + NT * e];
+            vn[e] = coil[crow + nx + NT * e];
+            sn[e] = w.sens[crow + nx + NT * e];
           }
         }
         fft<N, +1, RowLay<N>>(v, t, lds, rr_, s_tw);
