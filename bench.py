@@ -344,7 +344,8 @@ def learned_section(torch, B, steps):
     decade), report held-out losses (200 instances) and compare circulant with
     learned on the 256 x 256 x 12 slice: Split Bregman per-solve PCG counts and
     a PCG solve of A x = A x_true from 0 (iterations to 1e-3, relative residual
-    after 0..3 iterations)."""
+    after 0..3 iterations); the same solve for two harder operators (mu = 1e-2
+    and 1e-1) beside the superoptimal diagonal's count."""
     from paper_1710_01758_amd import learned as LD
     t0 = time.perf_counter()
     log("bench: learned - building datasets")
@@ -366,6 +367,17 @@ def learned_section(torch, B, steps):
                                gen.eval_seed(5))
     sb_scaled = LD.evaluate_on(inst_s, net, n_outer=20)
     ceiling = LD.evaluate_correction(inst, LD.superoptimal_correction(inst, nprobes=32))
+    # harder operators at 256 x 256 x 12: parameter set 2 (mu = 1e-2, inside
+    # the training range) and mu = 1e-1 (data term dominant, outside it); the
+    # probe-estimated superoptimal diagonal bounds what any spectrum
+    # correction can reach
+    harder = {}
+    for label, mu in (("mu_1e-2", 1e-2), ("mu_1e-1", 1e-1)):
+        inst_h = gen.make_instance(gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, mu=mu, lam=4e-3,
+                                                 gam=1e-3), gen.eval_seed(5))
+        ceil_h = LD.evaluate_correction(inst_h, LD.superoptimal_correction(inst_h, nprobes=32), n_outer=2)
+        harder[label] = {"pcg_from_zero": LD.pcg_first_solve(inst_h, net, curve=3),
+                         "superoptimal_probe_ceiling_iters_to_1e-3": ceil_h["pcg_iters_to_1e-3"]}
     for d in (train, held):
         d.ctx.close()
     net.close()
@@ -376,6 +388,7 @@ def learned_section(torch, B, steps):
                          "gap_closed": (circ - learned) / (circ - floor) if circ > floor else None},
         "slice_256x256x12": {"split_bregman": sb, "pcg_from_zero": pcg, "split_bregman_data_scale_1e3": sb_scaled,
                              "superoptimal_probe_ceiling": ceiling},
+        "slice_256x256x12_harder": harder,
         "seconds_total": round(time.perf_counter() - t0, 1),
     }
 
