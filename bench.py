@@ -128,7 +128,7 @@ def valu_roofline(avg_s):
         return None
     floor = instr * 4 / (SIMDS * PEAK_CLOCK_HZ)
     return {"bound": "alu", "valu_wave_instr_per_launch": int(instr), "floor_us_at_peak_clock": round(floor * 1e6, 2),
-            "frac": round(floor / avg_s, 4), "sustained_clock_GHz": float(f.get("sustained_clock_GHz", "nan"))}
+            "frac": round(floor / avg_s, 4)}
 
 
 def cpu_baseline(inst, min_seconds=10.0):
@@ -146,7 +146,16 @@ def cpu_baseline(inst, min_seconds=10.0):
         dt = time.perf_counter() - t0
         if dt >= min_seconds:
             break
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(count / dt, 4), "unit": "recons/s", "cores": 1, "kind": "oracle",
+            "host": f"{model}, os.cpu_count() = {os.cpu_count()}",
             "sample": f"{count} full reconstructions (20 outer iterations, circulant, build included) of one "
                       f"256x256x12 slice in FP64 NumPy with single-threaded pocketfft, {dt:.1f} s"}
 
@@ -396,8 +405,8 @@ def learned_section(torch, B, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=128, help="slices reconstructed per step")
     ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -406,8 +415,9 @@ def main():
                     help="skip the 512^2 x 32 slice, the ragged batch, the 2D-mask batch and the "
                          "parameter-set comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
-    ap.add_argument("--mode", choices=["full", "apply"], default="full",
-                    help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs)")
+    ap.add_argument("--mode", choices=["full", "apply", "apply2d"], default="full",
+                    help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs); "
+                         "apply2d: the same for the 2D-mask operator (256^2 x 12, batch of 32)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -418,6 +428,12 @@ def main():
 
     B.lib()
     torch.cuda.set_device(0)
+    if a.mode == "apply2d":
+        spec2 = gen.SliceSpec(256, 256, 12, 4.0, 24, mask_kind="2d", wavelet="db4", levels=3)
+        insts2 = [gen.make_instance(spec2, gen.eval_seed(6, i)) for i in range(32)]
+        ctx2, _ = B.context_for(insts2)
+        run_apply_mode(torch, ctx2, insts2)
+        return
     spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=a.scale)
     insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(a.batch)]
     ctx, ksp = B.context_for(insts)
