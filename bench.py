@@ -5,14 +5,18 @@ circulant preconditioner, and PCG iterations to 1e-3 for none / circulant.
 
 One step = build the preconditioner + one full reconstruction of every slice
 of the batch (all rows of the hot path: spectrum build, system operator,
-preconditioner, PCG updates, Split Bregman steps).  Inputs are synthetic
-(seeded phantoms, coil maps, masks, noise) and resident in HBM before timing.
+preconditioner, PCG updates, Split Bregman steps).  The batch is split into
+independent contexts (default 2 x 128 slices), each with its own stream and
+host thread, so that their kernel chains overlap on the GPU.  Inputs are
+synthetic (seeded phantoms, coil maps, masks, noise) and resident in HBM
+before timing.
 
 Prints ONE JSON line.  Single GPU only.
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import math
 import os
@@ -82,7 +86,8 @@ def run_apply_mode(torch, ctx, insts):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_hbm_traffic.md")
 VALU_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_valu.md")
-SIMDS, PEAK_CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs; a wave64 FP32 VALU op issues in 4 cycles
+SIMDS, PEAK_CLOCK_HZ = 1024, 2.4e9
+ROOFLINE_BATCH = 128  # slices per apply_A launch in the roofline measurement and the counter summaries  # 256 CUs x 4 SIMDs; a wave64 FP32 VALU op issues in 4 cycles
 
 
 def profile_fields(path):
@@ -407,7 +412,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=128, help="slices reconstructed per step")
+    ap.add_argument("--batch", type=int, default=256, help="slices reconstructed per step")
+    ap.add_argument("--contexts", type=int, default=2,
+                    help="independent contexts the batch is split into, each with its own stream and host thread")
     ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip training / evaluating the learned correction")
@@ -435,40 +442,63 @@ def main():
         run_apply_mode(torch, ctx2, insts2)
         return
     spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=a.scale)
-    insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(a.batch)]
-    ctx, ksp = B.context_for(insts)
     if a.mode == "apply":
+        insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(ROOFLINE_BATCH)]
+        ctx, _ = B.context_for(insts)
         run_apply_mode(torch, ctx, insts)
         return
-    split = ctx.autotune()
-    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    if a.contexts < 1 or a.batch % a.contexts:
+        print(json.dumps({"error": "--batch must be a multiple of --contexts"}))
+        sys.exit(2)
+    insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(a.batch)]
+    # the batch as `contexts` independent contexts, each with its own stream
+    # and host thread: their kernel chains interleave on the GPU (one's
+    # VALU-bound operator beside another's memory-bound passes)
+    per = a.batch // a.contexts
+    runs = []
+    for k in range(a.contexts):
+        st = torch.cuda.Stream()
+        c, kk = B.context_for(insts[k * per:(k + 1) * per], stream=st.cuda_stream)
+        runs.append({"ctx": c, "ksp": kk, "x": torch.zeros(c.image_elems, dtype=torch.complex64, device="cuda"),
+                     "stream": st})
+    split = [r["ctx"].autotune() for r in runs][0]
+    ctx, ksp, x = runs[0]["ctx"], runs[0]["ksp"], runs[0]["x"]
     torch.cuda.synchronize()
+    pool = cf.ThreadPoolExecutor(max_workers=a.contexts)
 
-    def step(kind="circulant"):
-        ctx.build_preconditioner(kind)
-        iters, _ = ctx.split_bregman_recon(ksp, x, n_outer=20, n_inner=1, tol=1e-3, maxit=1000)
+    def recon(r, kind="circulant"):
+        r["ctx"].build_preconditioner(kind)
+        iters, _ = r["ctx"].split_bregman_recon(r["ksp"], r["x"], n_outer=20, n_inner=1, tol=1e-3, maxit=1000)
         return iters
 
-    log(f"bench: warmup {a.warmup} steps, batch {a.batch}")
-    for _ in range(a.warmup):
-        step()
+    def steps_of(r, count):
+        # one context's share of `count` steps, back to back on its thread;
+        # returns the wall time of each reconstruction
+        times = []
+        for k in range(count):
+            ts = time.perf_counter()
+            r["iters"] = recon(r)
+            times.append((time.perf_counter() - ts) * 1e3)
+            if r is runs[0] and (k + 1) % 10 == 0:
+                log(f"bench: step {k + 1}/{count} done")
+        return times
+
+    log(f"bench: warmup {a.warmup} steps, batch {a.batch} as {a.contexts} contexts")
+    for f in [pool.submit(steps_of, r, a.warmup) for r in runs]:
+        f.result()
     torch.cuda.synchronize()
-    stream = torch.cuda.ExternalStream(ctx.stream) if ctx.stream else torch.cuda.current_stream()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
     t0 = time.perf_counter()
-    iters = None
-    evs[0].record(stream)
-    for k in range(a.steps):
-        iters = step()
-        evs[k + 1].record(stream)
-        log(f"bench: step {k + 1}/{a.steps} done")
+    futs = [pool.submit(steps_of, r, a.steps) for r in runs]
+    per_ctx_ms = [f.result() for f in futs]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(a.steps)])
+    iters = runs[0]["iters"]
+    step_ms = np.array(per_ctx_ms).ravel()
     value = a.batch * a.steps / dt
     ms_per_step = dt / a.steps * 1e3
+    pool.shutdown()
 
-    # the preconditioner build alone (Table 2 reports it separately)
+    # the preconditioner build alone (Table 2 reports it separately), one context
     for _ in range(2):
         ctx.build_preconditioner("circulant")
     torch.cuda.synchronize()
@@ -495,15 +525,23 @@ def main():
     single = n1 / (time.perf_counter() - t1)
 
     # PCG iterations to 1e-3: none vs circulant (first slice, every solve)
-    it_none = step("none")
-    it_circ = step("circulant")
+    it_none = recon(runs[0], "none")
+    it_circ = recon(runs[0], "circulant")
+    for r in runs:
+        r["ctx"].close()
+    del runs
 
-    # roofline of the dominant kernel (fused apply_A)
-    xa = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    # roofline of the dominant kernel (fused apply_A) over a batch of
+    # ROOFLINE_BATCH slices (the committed counter summaries' launch)
+    rinsts = insts[:ROOFLINE_BATCH]
+    rctx, _ = B.context_for(rinsts)
+    rsplit = rctx.autotune()
+    xa = torch.randn(rctx.image_elems, dtype=torch.complex64, device="cuda")
     ya = torch.empty_like(xa)
-    t_apply = time_apply_kernel(torch, ctx, xa, ya)
-    bytes_apply = apply_bytes([i.spec for i in insts])
+    t_apply = time_apply_kernel(torch, rctx, xa, ya)
+    bytes_apply = apply_bytes([i.spec for i in rinsts])
     achieved = bytes_apply / t_apply / 1e9
+    rctx.close()
 
     out = {
         "metric": "recons/s + PCG iters to 1e-3, 256^2 x 12 coils: circulant vs learned precond",
@@ -521,11 +559,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"split_bregman_recon 256x256, 12 coils, R=4 lines (24 centre), TV + db4 x3, "
                                f"mu=1e-3 lambda=gamma=4e-3, 20 outer iters, PCG tol 1e-3, circulant; "
-                               f"batch of {a.batch} slices per step, data_scale {a.scale:g}",
-                   "global_batch": a.batch, "m": 256, "n": 256, "ncoils": 12, "parallelism": "none (1 GPU)"},
+                               f"batch of {a.batch} slices per step as {a.contexts} concurrent contexts of {per} "
+                               f"(one stream and host thread each), data_scale {a.scale:g}",
+                   "global_batch": a.batch, "contexts": a.contexts, "m": 256, "n": 256, "ncoils": 12,
+                   "parallelism": "none (1 GPU)"},
         "step_ms_stats": {"median": round(float(np.median(step_ms)), 3), "p10": round(float(np.percentile(step_ms, 10)), 3),
-                          "p90": round(float(np.percentile(step_ms, 90)), 3), "source": "HIP events per step"},
-        "build_preconditioner_ms_batch": round(build_ms, 3),
+                          "p90": round(float(np.percentile(step_ms, 90)), 3),
+                          "source": "host wall clock of each context's reconstruction (the contexts run concurrently)"},
+        "build_preconditioner_ms_context": round(build_ms, 3),
+        "build_preconditioner_slices": per,
         "single_slice_recons_per_s": round(single, 3),
         "coil_split": {"batch": split[0], "single_slice": split1[0]},
         "pcg_iters": {
@@ -536,10 +578,11 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": (f"k_col_apply<256, 0, 0> (fused apply_A, {a.batch} slices per launch)" if split[0] == 1
-                                else f"k_col_apply<256, 0, 1> + <256, 0, 2> (apply_A, coil split {split[0]})"),
+                     "kernel": (f"k_col_apply<256, 0, 0> (fused apply_A, {ROOFLINE_BATCH} slices per launch)"
+                                if rsplit[0] == 1
+                                else f"k_col_apply<256, 0, 1> + <256, 0, 2> (apply_A, coil split {rsplit[0]})"),
                      "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": bytes_apply,
-                     "valu": valu_roofline(t_apply) if split[0] == 1 else None},
+                     "valu": valu_roofline(t_apply) if rsplit[0] == 1 else None},
     }
     if not a.no_extra:
         log("bench: 512x512x32 slice")
