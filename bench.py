@@ -6,7 +6,7 @@ circulant preconditioner, and PCG iterations to 1e-3 for none / circulant.
 One step = build the preconditioner + one full reconstruction of every slice
 of the batch (all rows of the hot path: spectrum build, system operator,
 preconditioner, PCG updates, Split Bregman steps).  The batch is split into
-independent contexts (default 2 x 128 slices), each with its own stream and
+independent contexts (default 3 x 128 slices), each with its own stream and
 host thread, so that their kernel chains overlap on the GPU.  Inputs are
 synthetic (seeded phantoms, coil maps, masks, noise) and resident in HBM
 before timing.
@@ -412,8 +412,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=256, help="slices reconstructed per step")
-    ap.add_argument("--contexts", type=int, default=2,
+    ap.add_argument("--batch", type=int, default=384, help="slices reconstructed per step")
+    ap.add_argument("--contexts", type=int, default=3,
                     help="independent contexts the batch is split into, each with its own stream and host thread")
     ap.add_argument("--scale", type=float, default=1.0, help="data scale (1e3 makes the shrinks active)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

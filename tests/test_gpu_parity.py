@@ -544,28 +544,28 @@ def test_split_bregman_tv_only_and_mixed_batch(torch, B):
     assert np.all(np.abs(free - lock) <= 1), (free, lock)
 
 
-def test_headline_workload_in_two_concurrent_contexts(torch, B):
-    """The benchmark's headline launch configuration at full size: 256 slices
+def test_headline_workload_in_concurrent_contexts(torch, B):
+    """The benchmark's headline launch configuration at full size: 384 slices
     of 256 x 256 x 12 (line mask R = 4, 24 centre lines, TV + 3-level db4,
     literal data scale, 20 outer iterations, circulant preconditioner, the
-    coil split the autotuner picks) as two contexts of 128 slices, each on its
-    own stream and host thread, reconstructing concurrently.  Two concurrent
-    runs agree bitwise; sampled slices agree with their stand-alone
-    reconstruction; and sampled slices, locked to the FP64 oracle's PCG
-    counts inside the same concurrent two-context run, match the oracle."""
+    coil split the autotuner picks) as three contexts of 128 slices, each on
+    its own stream and host thread, reconstructing concurrently.  Two
+    concurrent runs agree bitwise; sampled slices agree with their
+    stand-alone reconstruction; and sampled slices, locked to the FP64
+    oracle's PCG counts inside the same concurrent run, match the oracle."""
     import concurrent.futures as cf
     spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1.0)
-    nper, n_outer = 128, 20
-    _say("headline workload: generating 256 slices")
-    insts = [_inst(spec, gen.eval_seed(2, i)) for i in range(2 * nper)]
+    nctx, nper, n_outer = 3, 128, 20
+    _say(f"headline workload: generating {nctx * nper} slices")
+    insts = [_inst(spec, gen.eval_seed(2, i)) for i in range(nctx * nper)]
     runs = []
-    for k in range(2):
+    for k in range(nctx):
         st = torch.cuda.Stream()
         c, kk = B.context_for(insts[k * nper:(k + 1) * nper], stream=st.cuda_stream)
         c.autotune()
         runs.append((c, kk, torch.zeros(c.image_elems, dtype=torch.complex64, device="cuda")))
     torch.cuda.synchronize()
-    pool = cf.ThreadPoolExecutor(max_workers=2)
+    pool = cf.ThreadPoolExecutor(max_workers=nctx)
 
     def recon(r, lock=None):
         c, kk, x = r
@@ -576,18 +576,18 @@ def test_headline_workload_in_two_concurrent_contexts(torch, B):
             it, _ = c.split_bregman_recon(kk, x, n_outer=n_outer, lock=lock)
         return it, _host(x).reshape(nper, spec.m, spec.n)
 
-    def both(locks=(None, None)):
+    def concurrent(locks=(None,) * nctx):
         out = [f.result() for f in [pool.submit(recon, r, lk) for r, lk in zip(runs, locks)]]
         torch.cuda.synchronize()
         return np.concatenate([o[0] for o in out], axis=1), np.concatenate([o[1] for o in out])
 
     _say("  two concurrent free-running runs")
-    it_a, x_a = both()
-    it_b, x_b = both()
+    it_a, x_a = concurrent()
+    it_b, x_b = concurrent()
     assert np.array_equal(it_a, it_b) and np.array_equal(x_a, x_b)
     assert np.all(it_a[0] >= 1) and np.all(it_a <= 1000)
 
-    sampled = (0, 77, 128, 255)  # first and a middle slice of each context
+    sampled = (0, 77, 128, 255, 383)  # first, middle and last contexts
     for s in sampled:
         c1, k1 = _ctx(B, [insts[s]])
         c1.set_option(B.OPT_COIL_GROUPS, 1)
@@ -603,19 +603,19 @@ def test_headline_workload_in_two_concurrent_contexts(torch, B):
     # its own free-running counts
     lock = it_a.copy()
     refs = {}
-    for s in (77, 255):
+    for s in (77, 255, 300):
         it = insts[s]
         refs[s] = osb.split_bregman(it.kspace, it.sens, it.mask, spec.mu, spec.lam, spec.gam, "db4", 3,
                                     n_outer=n_outer, tol=1e-3, precond="circulant")
         lock[:, s] = refs[s].pcg_iters
         assert np.all(np.abs(it_a[:, s] - lock[:, s]) <= 1), (s, it_a[:, s], lock[:, s])
-    _say("  two concurrent runs locked to the oracle's counts on slices 77 and 255")
-    it_l, x_l = both((lock[:, :nper].copy(), lock[:, nper:].copy()))
+    _say("  concurrent run locked to the oracle's counts on slices 77, 255 and 300")
+    it_l, x_l = concurrent(tuple(lock[:, k * nper:(k + 1) * nper].copy() for k in range(nctx)))
     assert np.array_equal(it_l, lock)
     for s, ref in refs.items():
         err = H.rel_err(x_l[s], ref.x)
         _say(f"  slice {s}: rel err vs oracle {err:.2e}")
         assert err < 1e-4, (s, err)  # literal data scale: the shrinks stay inactive
-    same = [s for s in range(2 * nper) if s not in refs]
+    same = [s for s in range(nctx * nper) if s not in refs]
     assert max(H.rel_err(x_l[s], x_a[s]) for s in same[::37]) < 1e-6
     pool.shutdown()
