@@ -1,13 +1,16 @@
 // Host side of libpics.so: context, validation, workspace and the
 // orchestration of the kernels behind the C ABI declared in include/pics.h.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <sys/stat.h>
+#include <unistd.h>
 #include <string>
 #include <vector>
 
@@ -1280,6 +1283,9 @@ int pics_net_correction(pics_net* n, pics_ctx* c, const float* features, float* 
 // ~/.cache/pics_autotune.txt).
 namespace {
 
+std::atomic<long> tune_tmp_counter{0};
+std::mutex tune_mutex;  // one autotuning pass per process at a time (shared cache file)
+
 std::string tune_cache_path() {
   const char* p = getenv("PICS_TUNE_CACHE");
   if (p && *p) return p;
@@ -1324,18 +1330,19 @@ void write_tune_cache(const std::map<std::string, int>& m) {
   const std::string path = tune_cache_path();
   const size_t slash = path.rfind('/');
   if (slash != std::string::npos) {
-    std::string dir = path.substr(0, slash);
-    std::string cmd;  // create the directory without a shell
+    // create the directory (and its parents) without a shell
+    const std::string dir = path.substr(0, slash);
     for (size_t i = 1; i <= dir.size(); ++i)
-      if (i == dir.size() || dir[i] == '/') {
-        std::string part = dir.substr(0, i);
-        mkdir(part.c_str(), 0755);
-      }
+      if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
   }
-  FILE* f = fopen(path.c_str(), "w");
+  // written to a private file and renamed over the cache, so that a reader
+  // (another context or process) sees either the old or the new file whole
+  const std::string tmp = path + ".tmp." + std::to_string((long)getpid()) + "." +
+                          std::to_string(tune_tmp_counter.fetch_add(1));
+  FILE* f = fopen(tmp.c_str(), "w");
   if (!f) return;
   for (auto& kv : m) fprintf(f, "%s=%d\n", kv.first.c_str(), kv.second);
-  fclose(f);
+  if (fclose(f) != 0 || rename(tmp.c_str(), path.c_str()) != 0) remove(tmp.c_str());
 }
 
 int ensure_dpart(pics_ctx* c, int groups) {
@@ -1355,11 +1362,19 @@ extern "C" {
 
 int pics_autotune(pics_ctx* c, int32_t flags) {
   if (!c) return PICS_ERR_INVALID;
+  std::lock_guard<std::mutex> lock(tune_mutex);
   std::map<std::string, int> cache = (flags & PICS_TUNE_FORCE) ? std::map<std::string, int>() : read_tune_cache();
   bool changed = false;
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
+  struct Events {  // destroyed on every return path
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) hipEventDestroy(x);
+    }
+  } ev;
+  HIPCHK(c, hipEventCreate(&ev.e[0]));
+  HIPCHK(c, hipEventCreate(&ev.e[1]));
+  hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
   HIPCHK(c, launch_fill(c->stream, c->p, c->img_total, make_float2(1.f, 0.5f)));
   for (auto& g : c->groups) {
     if (g.mask_kind == PICS_MASK_2D) continue;  // the 2D path has no coil split
@@ -1400,8 +1415,6 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
     cache[key] = best;
     changed = true;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   ++c->tuning_gen;
   if (changed && !(flags & PICS_TUNE_NO_WRITE)) write_tune_cache(cache);
   return PICS_OK;
