@@ -30,7 +30,8 @@
  *     no other call allocates device memory).
  *   - calls are ordered on the stream given at creation and asynchronous
  *     unless they return host results (those synchronise that stream).
- *     One host thread per context at a time.
+ *     One host thread per context at a time; separate contexts (each on
+ *     its own stream) may be driven from separate host threads at once.
  *   - return value: 0 = OK, > 0 = warning, < 0 = error (see PICS_*).  Errors
  *     detected on the host are reported before anything is launched; the
  *     library never aborts.  pics_last_error() gives a message.
@@ -76,7 +77,7 @@ extern "C" {
 #define PICS_TERM_WAVELET_EXPLICIT 8 /* with PICS_TERM_GAMMA: evaluate gamma W^H W x through the wavelet
                                         analysis and synthesis instead of gamma x (apply_A only) */
 
-/* One slice.  m, n in {64, 128, 192, 224, 256, 320, 512}; ncoils >= 1;
+/* One slice.  m, n in {64, 128, 192, 224, 256, 320, 512, 1024}; ncoils >= 1;
  * levels: wavelet levels (each level needs even extents); mu, lambda,
  * gamma >= 0 and finite (Split Bregman needs lambda, gamma > 0: its shrink
  * thresholds are 1/lambda and 1/gamma, Algorithm 1 steps 6-8). */
