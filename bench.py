@@ -44,17 +44,19 @@ def apply_bytes(specs) -> int:
     return int(sum(8 * s.m * s.n * (s.ncoils + 2) for s in specs))
 
 
-def time_apply_kernel(torch, ctx, xd, yd, reps=50):
-    """Average duration of the fused apply_A kernel, from HIP events recorded
-    on the library's stream around `reps` back-to-back launches."""
+def time_apply_kernel(torch, ctx, xd, yd, reps=50, terms=None):
+    """Average duration of apply_A (by default the fused operator kernel), from
+    HIP events recorded on the library's stream around `reps` back-to-back
+    calls."""
     stream = torch.cuda.ExternalStream(ctx.stream) if ctx.stream else torch.cuda.current_stream()
+    kw = {} if terms is None else {"terms": terms}
     for _ in range(5):
-        ctx.apply_A(xd, yd)
+        ctx.apply_A(xd, yd, **kw)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        ctx.apply_A(xd, yd)
+        ctx.apply_A(xd, yd, **kw)
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps * 1e-3  # seconds
@@ -541,6 +543,10 @@ def main():
     t_apply = time_apply_kernel(torch, rctx, xa, ya)
     bytes_apply = apply_bytes([i.spec for i in rinsts])
     achieved = bytes_apply / t_apply / 1e9
+    # the same operator with gamma W^H W evaluated through the wavelet
+    # analysis and synthesis (W is unitary, so the fused kernel's gamma x is
+    # the same term)
+    t_explicit = time_apply_kernel(torch, rctx, xa, ya, reps=20, terms=B.TERM_ALL | B.TERM_WAVELET_EXPLICIT)
     rctx.close()
 
     out = {
@@ -583,6 +589,10 @@ def main():
                                 else f"k_col_apply<256, 0, 1> + <256, 0, 2> (apply_A, coil split {rsplit[0]})"),
                      "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": bytes_apply,
                      "valu": valu_roofline(t_apply) if rsplit[0] == 1 else None},
+        "apply_A_explicit_wavelet": {"avg_us": round(t_explicit * 1e6, 2),
+                                     "vs_fused": round(t_explicit / t_apply, 3),
+                                     "note": f"{ROOFLINE_BATCH} slices; gamma W^H W through the 3-level db4 analysis "
+                                             "and synthesis instead of gamma x"},
     }
     if not a.no_extra:
         log("bench: 512x512x32 slice")
