@@ -16,6 +16,8 @@ Modules
   pcg        preconditioned conjugate gradients (Complexity section)
   sb         Split Bregman, Algorithm 1
   learned    the learned spectrum correction: CNN, loss, probe statistics
+  coils      coil compression to virtual coils (Methods, Coil compression)
+  volume     the 3D operator and its circulant spectrum (Discussion)
 
 Parity status: every function here is pinned by the CPU tests against a dense
 matrix built from the definition, a closed form, an invariant or a library
