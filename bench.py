@@ -88,8 +88,8 @@ def run_apply_mode(torch, ctx, insts):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_hbm_traffic.md")
 VALU_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_valu.md")
-SIMDS, PEAK_CLOCK_HZ = 1024, 2.4e9
-ROOFLINE_BATCH = 128  # slices per apply_A launch in the roofline measurement and the counter summaries  # 256 CUs x 4 SIMDs; a wave64 FP32 VALU op issues in 4 cycles
+SIMDS, PEAK_CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs; a wave64 FP32 VALU op issues in 4 cycles
+ROOFLINE_BATCH = 128  # slices per apply_A launch in the roofline measurement and the counter summaries
 
 
 def profile_fields(path):
