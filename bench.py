@@ -142,17 +142,20 @@ def cpu_baseline(inst, min_seconds=10.0):
     """The FP64 oracle (Algorithm 1 as written, circulant preconditioner) on
     full 20-iteration reconstructions of one 256^2 x 12 slice, repeated until
     at least `min_seconds` of CPU work."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import sb as osb
     s = inst.spec
     t0 = time.perf_counter()
     count = 0
-    while True:
-        osb.split_bregman(inst.kspace, inst.sens, inst.mask, s.mu, s.lam, s.gam, s.wavelet, s.levels,
-                          n_outer=20, tol=1e-3, precond="circulant")
-        count += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds:
-            break
+    with threadpool_limits(limits=1):  # one core: BLAS and OpenMP pools held to one thread
+        while True:
+            osb.split_bregman(inst.kspace, inst.sens, inst.mask, s.mu, s.lam, s.gam, s.wavelet, s.levels,
+                              n_outer=20, tol=1e-3, precond="circulant")
+            count += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_seconds:
+                break
     model = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -165,6 +168,49 @@ def cpu_baseline(inst, min_seconds=10.0):
             "host": f"{model}, os.cpu_count() = {os.cpu_count()}",
             "sample": f"{count} full reconstructions (20 outer iterations, circulant, build included) of one "
                       f"256x256x12 slice in FP64 NumPy with single-threaded pocketfft, {dt:.1f} s"}
+
+
+def cpu_worker(seconds: float) -> None:
+    """One single-threaded oracle process of the all-cores baseline: full
+    reconstructions of the headline slice until `seconds` have passed; prints
+    {"count", "seconds"} as JSON."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import sb as osb
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3)
+    inst = gen.make_instance(spec, gen.eval_seed(2, 0))
+    t0 = time.perf_counter()
+    count = 0
+    with threadpool_limits(limits=1):
+        while True:
+            osb.split_bregman(inst.kspace, inst.sens, inst.mask, spec.mu, spec.lam, spec.gam, spec.wavelet,
+                              spec.levels, n_outer=20, tol=1e-3, precond="circulant")
+            count += 1
+            dt = time.perf_counter() - t0
+            if dt >= seconds:
+                break
+    print(json.dumps({"count": count, "seconds": dt}), flush=True)
+
+
+def cpu_baseline_all_cores(procs: int, seconds: float = 10.0):
+    """The oracle on `procs` host cores at once: independent single-threaded
+    processes, one reconstruction after another each (slices are independent,
+    so this is how a CPU would serve the batch).  Run before the GPU is
+    touched: the workers are plain child processes of a GPU-free parent."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    ps = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(seconds)],
+                           stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env) for _ in range(procs)]
+    rate, count, longest = 0.0, 0, 0.0
+    for p in ps:
+        out, err = p.communicate(timeout=600)
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed: {err[-2000:]}")
+        r = json.loads(out.strip().splitlines()[-1])
+        rate += r["count"] / r["seconds"]
+        count += r["count"]
+        longest = max(longest, r["seconds"])
+    return {"value": round(rate, 4), "unit": "recons/s", "cores": procs, "count": count, "seconds": round(longest, 1)}
 
 
 def workload_section(torch, B, insts, label, steps=2):
@@ -433,10 +479,24 @@ def main():
     ap.add_argument("--mode", choices=["full", "apply", "apply2d"], default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs); "
                          "apply2d: the same for the 2D-mask operator (256^2 x 12, batch of 32)")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="oracle processes of the all-cores CPU baseline (capped by the host's CPU count)")
     a = ap.parse_args()
+    if a.cpu_worker is not None:
+        cpu_worker(a.cpu_worker)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    cpu_all = None
+    if a.mode == "full" and not a.no_cpu_baseline:
+        # the all-cores oracle baseline first, while this process has not
+        # touched the GPU (its workers are child processes)
+        procs = max(1, min(a.cpu_procs, os.cpu_count() or 1))
+        log(f"bench: cpu baseline (oracle) on {procs} cores")
+        cpu_all = cpu_baseline_all_cores(procs)
 
     import torch
     from paper_1710_01758_amd import binding as B
@@ -627,8 +687,16 @@ def main():
     if not a.no_learned:
         out["learned"] = learned_section(torch, B, a.train_steps)
     if not a.no_cpu_baseline:
-        log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(insts[0])
+        log("bench: cpu baseline (oracle), one core")
+        one = cpu_baseline(insts[0])
+        out["cpu_baseline"] = {
+            "value": cpu_all["value"], "unit": "recons/s", "cores": cpu_all["cores"], "kind": "oracle",
+            "host": one["host"],
+            "sample": (f"{cpu_all['count']} full reconstructions (20 outer iterations, circulant, build included) of "
+                       f"one 256x256x12 slice by {cpu_all['cores']} concurrent single-threaded FP64 NumPy oracle "
+                       f"processes over {cpu_all['seconds']} s (slices are independent)"),
+            "single_core": {k: one[k] for k in ("value", "unit", "cores", "sample")},
+        }
     print(json.dumps(out), flush=True)
 
 

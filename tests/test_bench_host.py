@@ -56,3 +56,11 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_all_cores_oracle_baseline_sums_the_workers():
+    """Two single-threaded oracle workers, each at least one full
+    reconstruction: the reported rate is the sum of the workers' rates."""
+    r = bench.cpu_baseline_all_cores(2, seconds=0.1)
+    assert r["cores"] == 2 and r["count"] >= 2
+    assert 0 < r["value"] <= r["count"] / min(0.1, r["seconds"]) and r["unit"] == "recons/s"
