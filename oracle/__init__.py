@@ -21,7 +21,8 @@ Modules
 
 Parity status: every function here is pinned by the CPU tests against a dense
 matrix built from the definition, a closed form, an invariant or a library
-routine, except the active-shrink Split Bregman trajectory, which is pinned only
-piecewise (its operators and exact-case recurrences); that whole-trajectory
-result is "parity unpinned".
+routine.  Split Bregman is pinned by closed-form scalar recurrences with inactive
+shrinks and with active wavelet shrinks.  With active TV shrinks it is pinned only
+piecewise: its operators, the shrink, and those recurrences.  That whole
+trajectory is "parity unpinned".
 """
