@@ -26,8 +26,17 @@
  *     pics_sizes() returns the packed totals.
  *   - every data pointer is a device pointer owned by the caller; sizes are
  *     element counts.  The context borrows `sens` and `masks` until
- *     pics_destroy() and owns its workspace (allocated once in pics_create;
- *     no other call allocates device memory).
+ *     pics_destroy() and owns its workspace.  The fixed part is allocated in
+ *     pics_create.  Three grow-only tables are allocated, or enlarged, by the
+ *     first call that needs them, and kept until pics_destroy:
+ *       - the per-solve iteration history of split_bregman_recon
+ *         (2 x n_outer n_inner x nslices int32);
+ *       - the iteration-lock table (pcg_solve with maxit_per_slice,
+ *         split_bregman_recon with lock_iters);
+ *       - the coil-split partial sums, when pics_autotune or pics_set_option
+ *         selects a split G > 1 (G x image-packed c64).
+ *     Before it enlarges a table, such a call synchronises the stream.
+ *     Repeated calls with the same sizes allocate nothing.
  *   - calls are ordered on the stream given at creation and asynchronous
  *     unless they return host results (those synchronise that stream).
  *     One host thread per context at a time; separate contexts (each on

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libpics.so")
 PICS_OK = 0
 PICS_WARN_MAXIT = 1
 PICS_WARN_FALLBACK = 2
+PICS_ERR_INVALID, PICS_ERR_UNSUPPORTED, PICS_ERR_NONFINITE, PICS_ERR_BREAKDOWN = -1, -2, -3, -4
+PICS_ERR_NOT_POSITIVE, PICS_ERR_HIP, PICS_ERR_STATE = -5, -6, -7
 MASK_LINES, MASK_2D = 0, 1
 WAVELET = {"none": 0, "haar": 1, "db4": 2}
 PRECOND = {"none": 0, "jacobi": 1, "circulant": 2, "learned": 3}

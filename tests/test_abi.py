@@ -60,6 +60,8 @@ def test_binding_constants_match_header():
     assert d["PICS_OK"] == B.PICS_OK
     assert d["PICS_WARN_MAXIT"] == B.PICS_WARN_MAXIT
     assert d["PICS_WARN_FALLBACK"] == B.PICS_WARN_FALLBACK
+    for k in ("INVALID", "UNSUPPORTED", "NONFINITE", "BREAKDOWN", "NOT_POSITIVE", "HIP", "STATE"):
+        assert d["PICS_ERR_" + k] == getattr(B, "PICS_ERR_" + k)
     assert (d["PICS_MASK_LINES"], d["PICS_MASK_2D"]) == (B.MASK_LINES, B.MASK_2D)
     assert d["PICS_WAVELET_NONE"] == B.WAVELET["none"]
     assert d["PICS_WAVELET_HAAR"] == B.WAVELET["haar"]

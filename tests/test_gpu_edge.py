@@ -1,8 +1,9 @@
 """Degenerate and boundary cases of the GPU path: zero right-hand side,
 iteration cap, an empty sampling mask (with and without gamma), aliased or
 null buffers, an operator with no terms, zero Split Bregman iterations (the
-root-sum-of-squares start), the smallest slice with one coil, and a slice with
-many coils."""
+root-sum-of-squares start), the smallest slice with one coil, a slice with
+many coils, a non-finite right-hand side in one slice of a batch, and the
+zero operator (PCG breakdown)."""
 import sys
 
 import numpy as np
@@ -151,3 +152,55 @@ def test_one_coil_and_many_coils(torch, B, nc):
     ctx.build_preconditioner("circulant", khat=khat)
     k = opre.circulant_k(it.sens, r2d, spec.mu, spec.lam, spec.gam)
     assert np.max(np.abs(_host(khat).reshape(64, 64) - k)) / k.max() < 1e-5
+
+
+def _raw_pcg(B, ctx, b, x, tol, maxit):
+    """pcg_solve through the C ABI without the binding's exception, so the
+    per-slice iteration counts and status words can be read after an error."""
+    n = ctx.n
+    iters, rel, st = np.zeros(n, np.int32), np.zeros(n, np.float64), np.zeros(n, np.int32)
+    i32, f64 = B.ctypes.POINTER(B.ctypes.c_int32), B.ctypes.POINTER(B.ctypes.c_double)
+    rc = ctx.L.pcg_solve(ctx.h, B._ptr(b), B._ptr(x), float(tol), int(maxit), None, iters.ctypes.data_as(i32),
+                         rel.ctypes.data_as(f64), st.ctypes.data_as(i32))
+    return rc, iters, st
+
+
+def test_nonfinite_rhs_ends_only_its_slice(torch, B):
+    """A NaN in one slice's right-hand side: that slice's PCG stops with the
+    non-finite status at its first step size, the call reports
+    PICS_ERR_NONFINITE, and the other slice of the batch converges exactly as
+    it does alone."""
+    _say("edge: NaN in one slice's rhs")
+    its = [gen.make_instance(gen.CFG1, gen.eval_seed(1, i)) for i in range(2)]
+    ctx, _ = B.context_for(its)
+    ctx.build_preconditioner("circulant")
+    bh = np.concatenate([gen.random_image(40 + i, 64, 64).ravel() for i in range(2)]).astype(np.complex64)
+    bh[123] = np.nan
+    b = B.to_device(bh)
+    x = torch.zeros_like(b)
+    rc, iters, st = _raw_pcg(B, ctx, b, x, 1e-3, 100)
+    assert rc == B.PICS_ERR_NONFINITE, rc
+    assert st[0] == B.PICS_ERR_NONFINITE and iters[0] <= 1, (st, iters)
+    assert st[1] == 1 and 0 < iters[1] < 100, (st, iters)
+    c1, _ = B.context_for(its[1:])
+    c1.build_preconditioner("circulant")
+    b1 = B.to_device(bh[64 * 64:])
+    x1 = torch.zeros_like(b1)
+    it1, _, s1, rc1 = c1.pcg_solve(b1, x1, 1e-3, 100)
+    assert rc1 == B.PICS_OK and it1[0] == iters[1]
+    assert H.rel_err(_host(x)[64 * 64:], _host(x1)) < 1e-6
+
+
+def test_zero_operator_is_a_breakdown(torch, B):
+    """mu = lambda = gamma = 0 makes A = 0, so p^H A p = 0 at the first step:
+    the solve ends with PICS_ERR_BREAKDOWN instead of dividing by zero."""
+    _say("edge: A = 0")
+    spec = gen.SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1, mu=0.0, lam=0.0, gam=0.0)
+    it = gen.make_instance(spec, gen.eval_seed(1))
+    ctx, _ = B.context_for([it])
+    ctx.build_preconditioner("none")
+    b = B.to_device(gen.random_image(50, 64, 64).astype(np.complex64).ravel())
+    x = torch.zeros_like(b)
+    rc, iters, st = _raw_pcg(B, ctx, b, x, 1e-3, 100)
+    assert rc == B.PICS_ERR_BREAKDOWN and st[0] == B.PICS_ERR_BREAKDOWN, (rc, st)
+    assert np.all(np.isfinite(_host(x)))
