@@ -566,6 +566,24 @@ def main():
     ms_per_step = dt / a.steps * 1e3
     pool.shutdown()
 
+    # host-to-device bandwidth from pinned memory: what a slice's inputs
+    # (zero-filled k-space and coil maps, c64) would cost if they arrived from
+    # the host instead of being resident (the timed steps above exclude it)
+    h2d_bytes = 256 * 2**20
+    hbuf = torch.empty(h2d_bytes, dtype=torch.uint8, pin_memory=True)
+    dbuf = torch.empty(h2d_bytes, dtype=torch.uint8, device="cuda")
+    dbuf.copy_(hbuf, non_blocking=True)
+    torch.cuda.synchronize()
+    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h0.record()
+    for _ in range(5):
+        dbuf.copy_(hbuf, non_blocking=True)
+    h1.record()
+    h1.synchronize()
+    h2d_gbs = 5 * h2d_bytes / (h0.elapsed_time(h1) * 1e-3) / 1e9
+    slice_in_bytes = 2 * 8 * spec.m * spec.n * spec.ncoils
+    del hbuf, dbuf
+
     # the preconditioner build alone (Table 2 reports it separately), one context
     for _ in range(2):
         ctx.build_preconditioner("circulant")
@@ -638,6 +656,9 @@ def main():
         "step_ms_stats": {"median": round(float(np.median(step_ms)), 3), "p10": round(float(np.percentile(step_ms, 10)), 3),
                           "p90": round(float(np.percentile(step_ms, 90)), 3),
                           "source": "host wall clock of each context's reconstruction (the contexts run concurrently)"},
+        "h2d": {"GB_per_s": round(h2d_gbs, 1), "input_bytes_per_slice": slice_in_bytes,
+                "recons_per_s_if_inputs_come_from_host": round(h2d_gbs * 1e9 / slice_in_bytes, 1),
+                "note": "pinned host to device, 256 MiB copies; inputs per slice = k-space + coil maps (c64)"},
         "build_preconditioner_ms_context": round(build_ms, 3),
         "build_preconditioner_slices": per,
         "single_slice_recons_per_s": round(single, 3),
