@@ -172,7 +172,7 @@ template <> struct Plan<192> { static constexpr int NT = 16; using R = Radices<1
 template <> struct Plan<224> { static constexpr int NT = 8; using R = Radices<28, 4, 2>; };
 template <> struct Plan<256> { static constexpr int NT = 16; using R = Radices<16, 16>; };
 template <> struct Plan<320> { static constexpr int NT = 16; using R = Radices<20, 4, 4>; };
-template <> struct Plan<512> { static constexpr int NT = 32; using R = Radices<16, 16, 2>; };
+template <> struct Plan<512> { static constexpr int NT = 64; using R = Radices<8, 8, 8>; };
 template <> struct Plan<1024> { static constexpr int NT = 64; using R = Radices<16, 16, 4>; };
 
 // Offsets of each length's table inside the packed twiddle buffer

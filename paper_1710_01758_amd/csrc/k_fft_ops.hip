@@ -163,10 +163,9 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
     const float2* __restrict__ S = w.sens + sd.coil + t * n + col;
     const int plane = M * n;
     // the next coil's maps are prefetched, except at length 1024, where the
-    // extra registers would spill, and at 320 and 512, where the registers
-    // they free (at 320 with the halo loaded late) give two waves per SIMD
-    // instead of one
-    constexpr bool PREFETCH = M < 1024 && M != 320 && M != 512;
+    // extra registers would spill, and at 320, where the registers they free
+    // (with the halo loaded late) give two waves per SIMD instead of one
+    constexpr bool PREFETCH = M < 1024 && M != 320;
     // one coil: S_c p -> FFT -> mask / m -> IFFT -> += conj(S_c) (.); `cur`
     // holds S_c, and with PF `nxt` receives the maps of coil pf once S_c p is
     // formed, so that the load runs during the transforms.  PF is a template

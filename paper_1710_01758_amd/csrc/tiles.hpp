@@ -25,8 +25,8 @@ struct ColCfg {
 template <int M>
 struct ApplyCfg : ColCfg<M> {
   // workgroups per CU the register allocation must allow: two waves per
-  // SIMD at 320 (4-wave workgroups) and 512 (2-wave workgroups)
-  static constexpr int MIN_BLOCKS = M == 320 ? 2 : M == 512 ? 4 : 1;
+  // SIMD at 320 and 512 (4-wave workgroups)
+  static constexpr int MIN_BLOCKS = M == 320 || M == 512 ? 2 : 1;
 };
 template <int M>
 struct ApplyDual { static constexpr bool value = M <= 256; };
