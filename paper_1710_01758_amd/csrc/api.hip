@@ -178,7 +178,7 @@ struct GroupFork {
     }
     return e;
   }
-  ~GroupFork() { join(); }
+  ~GroupFork() { (void)join(); }
 };
 
 // Ws whose group table is the group's slice list (grid.y -> slice)
@@ -359,7 +359,10 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   c->sens = (const float2*)sens;
   c->masks = masks;
   c->desc.assign(descs, descs + nslices);
-  hipGetDevice(&c->device);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return PICS_ERR_HIP;
+  }
 
   std::map<std::tuple<int, int, int>, int> gidx;
   for (int s = 0; s < nslices; ++s) {
@@ -441,8 +444,8 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   }
   if (hipHostMalloc((void**)&c->st_host, sizeof(PcgState) * nslices, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->flag_host, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
-    if (c->st_host) hipHostFree(c->st_host);
-    hipFree(c->block);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    (void)hipFree(c->block);
     delete c;
     return PICS_ERR_HIP;
   }
@@ -470,12 +473,12 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
     }
   }
   if (!ok) {
-    for (auto st : c->side) hipStreamDestroy(st);
-    for (auto ev : c->side_done) hipEventDestroy(ev);
-    if (c->fork_ev) hipEventDestroy(c->fork_ev);
-    hipHostFree(c->st_host);
-    hipHostFree(c->flag_host);
-    hipFree(c->block);
+    for (auto st : c->side) (void)hipStreamDestroy(st);
+    for (auto ev : c->side_done) (void)hipEventDestroy(ev);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    (void)hipHostFree(c->st_host);
+    (void)hipHostFree(c->flag_host);
+    (void)hipFree(c->block);
     delete c;
     return PICS_ERR_HIP;
   }
@@ -485,18 +488,19 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
 
 int pics_destroy(pics_ctx* c) {
   if (!c) return PICS_ERR_INVALID;
-  hipStreamSynchronize(c->stream);
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-  if (c->hist) hipFree(c->hist);
-  if (c->dpart) hipFree(c->dpart);
-  for (auto st : c->side) hipStreamDestroy(st);
-  for (auto ev : c->side_done) hipEventDestroy(ev);
-  if (c->fork_ev) hipEventDestroy(c->fork_ev);
-  if (c->lock_block) hipFree(c->lock_block);
-  if (c->st_host) hipHostFree(c->st_host);
-  if (c->flag_host) hipHostFree(c->flag_host);
-  if (c->block) hipFree(c->block);
+  // best-effort release: errors are ignored on the way out
+  (void)hipStreamSynchronize(c->stream);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->hist) (void)hipFree(c->hist);
+  if (c->dpart) (void)hipFree(c->dpart);
+  for (auto st : c->side) (void)hipStreamDestroy(st);
+  for (auto ev : c->side_done) (void)hipEventDestroy(ev);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->lock_block) (void)hipFree(c->lock_block);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->flag_host) (void)hipHostFree(c->flag_host);
+  if (c->block) (void)hipFree(c->block);
   delete c;
   return PICS_OK;
 }
@@ -628,8 +632,6 @@ int pics_fft2(pics_ctx* c, const void* in, void* out, int32_t inverse) {
 int pics_wavelet(pics_ctx* c, const void* in, void* out, int32_t inverse) {
   if (!c) return PICS_ERR_INVALID;
   if (!in || !out || in == out) return fail(c, PICS_ERR_INVALID, "wavelet: null or aliased buffers");
-  const Ws w = make_ws(c);
-  const Simple S = make_simple(c);
   for (int s = 0; s < c->nslices; ++s) {
     if (c->sl[s].levels == 0)
       HIPCHK(c, hipMemcpyAsync((float2*)out + c->sl[s].img, (const float2*)in + c->sl[s].img,
@@ -847,12 +849,12 @@ int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget, int n_
   }
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
   if (rc) {
-    if (e == hipSuccess) hipGraphDestroy(graph);
+    if (e == hipSuccess) (void)hipGraphDestroy(graph);
     return rc;
   }
   HIPCHK(c, e);
   const hipError_t ei = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   HIPCHK(c, ei);
   c->graph_key = key;
   return PICS_OK;
@@ -1130,8 +1132,8 @@ int pics_net_create(pics_net** out, int32_t batch_max, void* stream) {
   }
   if (hipHostMalloc((void**)&n->loss_host, sizeof(double) * batch_max * kNetGrid, hipHostMallocDefault) != hipSuccess ||
       hipMemset(n->block, 0, total) != hipSuccess) {
-    if (n->loss_host) hipHostFree(n->loss_host);
-    hipFree(n->block);
+    if (n->loss_host) (void)hipHostFree(n->loss_host);
+    (void)hipFree(n->block);
     delete n;
     return PICS_ERR_HIP;
   }
@@ -1141,9 +1143,9 @@ int pics_net_create(pics_net** out, int32_t batch_max, void* stream) {
 
 int pics_net_destroy(pics_net* n) {
   if (!n) return PICS_ERR_INVALID;
-  hipStreamSynchronize(n->stream);
-  if (n->loss_host) hipHostFree(n->loss_host);
-  if (n->block) hipFree(n->block);
+  (void)hipStreamSynchronize(n->stream);
+  if (n->loss_host) (void)hipHostFree(n->loss_host);
+  if (n->block) (void)hipFree(n->block);
   delete n;
   return PICS_OK;
 }
@@ -1295,7 +1297,7 @@ std::string tune_cache_path() {
 
 std::string device_tag() {
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
   char buf[128];
@@ -1369,7 +1371,7 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
     hipEvent_t e[2] = {nullptr, nullptr};
     ~Events() {
       for (hipEvent_t x : e)
-        if (x) hipEventDestroy(x);
+        if (x) (void)hipEventDestroy(x);
     }
   } ev;
   HIPCHK(c, hipEventCreate(&ev.e[0]));

@@ -180,9 +180,9 @@ int pics3d_create(pics3d_ctx** out, const pics3d_desc* d, const void* sens, cons
             hipHostMalloc((void**)&c->flag_host, sizeof(int)) == hipSuccess &&
             hipHostMalloc((void**)&c->scal_host, sizeof(double) * 8) == hipSuccess;
   if (!ok) {
-    if (c->flag_host) hipHostFree(c->flag_host);
-    if (c->scal_host) hipHostFree(c->scal_host);
-    hipFree(c->block);
+    if (c->flag_host) (void)hipHostFree(c->flag_host);
+    if (c->scal_host) (void)hipHostFree(c->scal_host);
+    (void)hipFree(c->block);
     delete c;
     return PICS_ERR_HIP;
   }
@@ -192,10 +192,11 @@ int pics3d_create(pics3d_ctx** out, const pics3d_desc* d, const void* sens, cons
 
 int pics3d_destroy(pics3d_ctx* c) {
   if (!c) return PICS_ERR_INVALID;
-  hipStreamSynchronize(c->stream);
-  hipHostFree(c->flag_host);
-  hipHostFree(c->scal_host);
-  hipFree(c->block);
+  // best-effort release: errors are ignored on the way out
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipHostFree(c->flag_host);
+  (void)hipHostFree(c->scal_host);
+  (void)hipFree(c->block);
   delete c;
   return PICS_OK;
 }
