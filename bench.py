@@ -86,6 +86,26 @@ def run_apply_mode(torch, ctx, insts):
                       "achieved_GBs": round(b / t_apply / 1e9, 1), "copy_cal_bytes": COPY_CAL_BYTES}), flush=True)
 
 
+def run_pcg_mode(torch, ctx, iters=10, reps=5):
+    """Iteration-locked PCG solves (every slice runs exactly `iters`
+    iterations from x = 0, circulant preconditioner), so that every launch
+    of the PCG kernels works on the whole batch (for kernel traces)."""
+    ctx.build_preconditioner("circulant")
+    b = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    x = torch.zeros_like(b)
+    lock = [iters] * ctx.n
+    ctx.pcg_solve(b, x, 0.0, 0, maxit_per_slice=lock)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x.zero_()
+        ctx.pcg_solve(b, x, 0.0, 0, maxit_per_slice=lock)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"pcg_iters": iters, "slices": ctx.n, "ms_per_solve": round(dt * 1e3, 3),
+                      "us_per_iteration": round(dt / iters * 1e6, 2)}), flush=True)
+
+
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_hbm_traffic.md")
 VALU_PROFILE = os.path.join(ROOT, "profiles", "apply_A_256x256x12_batch128_valu.md")
 SIMDS, PEAK_CLOCK_HZ = 1024, 2.4e9  # 256 CUs x 4 SIMDs; a wave64 FP32 VALU op issues in 4 cycles
@@ -476,9 +496,10 @@ def main():
                     help="skip the 512^2 x 32 slice, the ragged batch, the 2D-mask batch and the "
                          "parameter-set comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
-    ap.add_argument("--mode", choices=["full", "apply", "apply2d"], default="full",
+    ap.add_argument("--mode", choices=["full", "apply", "apply2d", "pcg"], default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs); "
-                         "apply2d: the same for the 2D-mask operator (256^2 x 12, batch of 32)")
+                         "apply2d: the same for the 2D-mask operator (256^2 x 12, batch of 32); "
+                         "pcg: iteration-locked PCG solves over 128 slices (for kernel traces)")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-procs", type=int, default=16,
                     help="oracle processes of the all-cores CPU baseline (capped by the host's CPU count)")
@@ -510,10 +531,13 @@ def main():
         run_apply_mode(torch, ctx2, insts2)
         return
     spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=a.scale)
-    if a.mode == "apply":
+    if a.mode in ("apply", "pcg"):
         insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(ROOFLINE_BATCH)]
         ctx, _ = B.context_for(insts)
-        run_apply_mode(torch, ctx, insts)
+        if a.mode == "apply":
+            run_apply_mode(torch, ctx, insts)
+        else:
+            run_pcg_mode(torch, ctx)
         return
     if a.contexts < 1 or a.batch % a.contexts:
         print(json.dumps({"error": "--batch must be a multiple of --contexts"}))
