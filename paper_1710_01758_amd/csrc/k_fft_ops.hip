@@ -357,29 +357,48 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
     alpha = float(a);
   }
 
+  // every load of the row is issued before the first store (x and r are
+  // written in place), so the loads of all elements are in flight together
   float2 v[E];
   double rrp = 0.0, bbp = 0.0, rhop = 0.0;
+  if (mode == RU_UPDATE) {
+    float2 pv[E], xv[E], qv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long long idx = rowbase + t + NT * e;
+      pv[e] = pn[idx];
+      xv[e] = x[idx];
+      v[e] = r[idx];
+      qv[e] = q[idx];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long long idx = rowbase + t + NT * e;
+      x[idx] = make_float2(xv[e].x + alpha * pv[e].x, xv[e].y + alpha * pv[e].y);
+      v[e] = make_float2(v[e].x - alpha * qv[e].x, v[e].y - alpha * qv[e].y);
+      r[idx] = v[e];
+    }
+  } else {
+    float2 bv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long long idx = rowbase + t + NT * e;
+      bv[e] = b[idx];
+      v[e] = q[idx];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v[e] = csub(bv[e], v[e]);
+      bbp += (double)bv[e].x * bv[e].x + (double)bv[e].y * bv[e].y;
+      r[rowbase + t + NT * e] = v[e];
+    }
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const long long idx = rowbase + t + NT * e;
-    float2 rv;
-    if (mode == RU_UPDATE) {
-      const float2 pnv = pn[idx];
-      const float2 xv = x[idx];
-      x[idx] = make_float2(xv.x + alpha * pnv.x, xv.y + alpha * pnv.y);
-      const float2 ro = r[idx], qv = q[idx];
-      rv = make_float2(ro.x - alpha * qv.x, ro.y - alpha * qv.y);
-    } else {
-      const float2 bv = b[idx], qv = q[idx];
-      rv = csub(bv, qv);
-      bbp += (double)bv.x * bv.x + (double)bv.y * bv.y;
-    }
-    r[idx] = rv;
-    const double a2 = (double)rv.x * rv.x + (double)rv.y * rv.y;
+    const double a2 = (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
     rrp += a2;
-    if (pk == PK_JACOBI) rhop += (double)w.jac[idx] * a2;
+    if (pk == PK_JACOBI) rhop += (double)w.jac[rowbase + t + NT * e] * a2;
     if (pk == PK_NONE) rhop += a2;
-    v[e] = rv;
   }
   rrp = block_sum_f64(rrp, red);
   if (threadIdx.x == 0) part_ptr(w.part, s, P_RR)[blockIdx.x] = rrp;
