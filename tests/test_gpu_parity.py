@@ -202,6 +202,33 @@ def test_pcg_iteration_locked_and_free_running(torch, B, cfg, precond):
     assert true_rel <= 1.05e-3, true_rel
 
 
+@pytest.mark.parametrize("groups", [1, 4])
+def test_pcg_locked_cfg3_512x512x32(torch, B, groups):
+    """The 512^2 x 32 slice (variable-density lines, R = 6): three circulant
+    PCG iterations (two reach 1e-3; the third runs past it), locked on both
+    sides, with the fused operator and with its coil loop split over 4
+    workgroups per column tile (the split the autotuner picks for one such
+    slice).  Covers the length-512 transforms of every PCG pass."""
+    _say(f"pcg cfg3 circulant, coil groups {groups}")
+    it = _inst(gen.CFG3, gen.eval_seed(3))
+    s = it.spec
+    r2d = it.mask2d.astype(np.float64)
+    A = lambda v: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
+    minv = osb.make_minv("circulant", it.sens, r2d, s.mu, s.lam, s.gam)
+    b = _rhs(it)
+    ref = opcg.pcg(A, b, np.zeros_like(b), minv, 0.0, 3)
+    ctx, _ = _ctx(B, [it])
+    ctx.set_option(B.OPT_COIL_GROUPS, groups)
+    ctx.build_preconditioner("circulant")
+    bd = B.to_device(b.astype(np.complex64).ravel())
+    xd = torch.zeros_like(bd)
+    iters, _, _, _ = ctx.pcg_solve(bd, xd, 0.0, 0, maxit_per_slice=[ref.iters])
+    assert iters[0] == ref.iters
+    err = H.rel_err(_host(xd).reshape(s.m, s.n), ref.x)
+    _say(f"  {ref.iters} iterations, rel err vs oracle {err:.2e}")
+    assert err < 1e-4, err
+
+
 def test_pcg_locked_cfg2_longer_run(torch, B):
     """Eight iterations of unpreconditioned CG at 256^2 x 12 stay within 1e-4."""
     _say("pcg cfg2 none locked 8")
