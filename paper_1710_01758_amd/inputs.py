@@ -176,8 +176,9 @@ def random_2d_mask(m: int, n: int, accel: float, centre: int, rng: np.random.Gen
     total = int(round(m * n / accel))
     mask = np.zeros((m, n), np.uint8)
     half = centre // 2
-    cu = np.abs(signed_freq(m)) < max(half, 1)
-    cv = np.abs(signed_freq(n)) < max(half, 1)
+    fu_s, fv_s = signed_freq(m), signed_freq(n)
+    cu = (fu_s >= -half) & (fu_s < centre - half)    # exactly `centre` rows, DC included
+    cv = (fv_s >= -half) & (fv_s < centre - half)
     mask[np.ix_(cu, cv)] = 1
     k = total - int(mask.sum())
     if k > 0:

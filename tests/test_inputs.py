@@ -59,3 +59,19 @@ def test_cfg4_batch_recipe():
     assert all(8 <= s.ncoils <= 32 for s in specs)
     assert {s.accel for s in specs} <= set(gen.CFG4_ACCELS)
     assert all(s.centre == 2 * round(6 * s.m / 128) for s in specs)
+
+
+@pytest.mark.parametrize("m,n,C", [(256, 256, 24), (64, 64, 12), (128, 192, 7), (64, 64, 1)])
+def test_random_2d_mask_centre_block_is_exactly_centre_square(m, n, C):
+    """The fully sampled centre of a 2D mask (Methods, Undersampling, second
+    scheme) is a C x C block of the lowest frequencies, DC included: its rows
+    are the C signed frequencies -C//2 .. C - C//2 - 1, likewise its columns."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    mask = gen.random_2d_mask(m, n, 4.0, C, rng)
+    fu, fv = gen.signed_freq(m), gen.signed_freq(n)
+    rows = (fu >= -(C // 2)) & (fu < C - C // 2)
+    cols = (fv >= -(C // 2)) & (fv < C - C // 2)
+    assert rows.sum() == C and cols.sum() == C
+    assert np.all(mask[np.ix_(rows, cols)] == 1)
+    assert mask[0, 0] == 1
+    assert mask.sum() == int(round(m * n / 4.0))
