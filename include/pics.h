@@ -134,6 +134,26 @@ int build_preconditioner(pics_ctx* ctx, int32_t kind, const float* correction, f
  * computed with FP32 FFTs. */
 int apply_A(pics_ctx* ctx, const void* x, void* y, int32_t terms);
 
+/* apply_A for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same operator and terms as apply_A (x, y as there), with every column
+ * tile's coil loop split over min(coil_groups, coil count of the size group)
+ * workgroups whose partial data terms (coil_groups x image-packed c64) go to
+ * a static device array of the library, PICS_NOALLOC_SCRATCH_BYTES per GPU,
+ * instead of the context's grow-only split table; coil_groups = 1 is the
+ * fused single pass and touches no scratch.  Slices with 2D masks run as in
+ * apply_A, through the context's coil workspace.  Allocates nothing and does
+ * not synchronise; the array's device address is looked up by pics_create
+ * (once per GPU) and the array is held until the process ends.
+ * PICS_ERR_INVALID if coil_groups is outside 1..64 or the split needs more
+ * than PICS_NOALLOC_SCRATCH_BYTES (8 bytes x image elements x split); nothing
+ * is launched then.  Every call on one GPU shares the array, which keeps the
+ * last call's partial sums (each is written before it is read, so nothing
+ * needs to start at zero): calls that overlap on one GPU (other streams,
+ * contexts or host threads) race and must be ordered by the caller. */
+#define PICS_NOALLOC_SCRATCH_BYTES (32 << 20)
+int apply_A_noalloc(pics_ctx* ctx, const void* x, void* y, int32_t terms, int32_t coil_groups);
+
 /* z = M^{-1} r = F^H diag(k)^{-1} F r (Eq. precon); needs a CIRCULANT or
  * LEARNED build.  r and z image-packed c64, must not alias. */
 int apply_Minv(pics_ctx* ctx, const void* r, void* z);

@@ -63,6 +63,7 @@ def signatures():
         "pics_sizes": (ctypes.c_int, [vp, pi64, pi64, pi64]),
         "build_preconditioner": (ctypes.c_int, [vp, i32, vp, vp]),
         "apply_A": (ctypes.c_int, [vp, vp, vp, i32]),
+        "apply_A_noalloc": (ctypes.c_int, [vp, vp, vp, i32, i32]),
         "apply_Minv": (ctypes.c_int, [vp, vp, vp]),
         "pics_fft2": (ctypes.c_int, [vp, vp, vp, i32]),
         "pics_wavelet": (ctypes.c_int, [vp, vp, vp, i32]),
@@ -197,6 +198,9 @@ class Context:
 
     def apply_A(self, x, y, terms: int = TERM_ALL) -> int:
         return self._check(self.L.apply_A(self.h, _ptr(x), _ptr(y), terms))
+
+    def apply_A_noalloc(self, x, y, terms: int = TERM_ALL, coil_groups: int = 1) -> int:
+        return self._check(self.L.apply_A_noalloc(self.h, _ptr(x), _ptr(y), terms, int(coil_groups)))
 
     def apply_Minv(self, r, z) -> int:
         return self._check(self.L.apply_Minv(self.h, _ptr(r), _ptr(z)))

@@ -98,8 +98,41 @@ struct pics_ctx {
 
   float2* dpart = nullptr;       // per-coil-group partial data terms [groups][image-packed]
   int dpart_groups = 0;
+  float2* scratch_dev = nullptr; // device address of `scratch` on this context's GPU (apply_A_noalloc)
   int tuning_gen = 0;            // bumped whenever a coil split or dpart changes
 };
+
+// Scratch of apply_A_noalloc, for callers that cannot allocate: the coil
+// groups' partial data terms.  Every GPU that loads the library holds its own
+// copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels and copies take the per-device
+// address that scratch_address() resolves, never the array's name.
+static __device__ __align__(256) float2 scratch[PICS_NOALLOC_SCRATCH_BYTES / sizeof(float2)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float2* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current: looked up
+// once per device, then served from the table.
+hipError_t scratch_address(int device, float2** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = (float2*)p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -190,13 +223,20 @@ Ws ws_for(const pics_ctx* c, const pics_ctx::Group& g) {
 
 // The system operator on one size group: the fused column-tile kernel for
 // line masks, the three-pass 2D-transform path for 2D masks.
+// split, dpart: coil split of the line-mask kernel and the buffer of its
+// partial sums (split 0: the group's tuned split and the context's table).
 hipError_t launch_operator(pics_ctx* c, const pics_ctx::Group& g, int mode, int terms, int pk, double tol,
-                           const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out) {
+                           const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
+                           int split = 0, float2* dpart = nullptr) {
   if (g.mask_kind == PICS_MASK_2D)
     return launch_apply2d(make_launch(c, g), ws_for(c, g), mode, terms, pk, tol, xin, zsrc, pold, pn, out,
                           c->coiltmp);
-  return launch_col_apply(make_launch(c, g), ws_for(c, g), mode, terms, pk, tol, xin, zsrc, pold, pn, out,
-                          g.coil_groups, c->dpart, c->img_total);
+  if (split == 0) {
+    split = g.coil_groups;
+    dpart = c->dpart;
+  }
+  return launch_col_apply(make_launch(c, g), ws_for(c, g), mode, terms, pk, tol, xin, zsrc, pold, pn, out, split,
+                          dpart, c->img_total);
 }
 
 }  // namespace
@@ -359,7 +399,7 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   c->sens = (const float2*)sens;
   c->masks = masks;
   c->desc.assign(descs, descs + nslices);
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess || scratch_address(c->device, &c->scratch_dev) != hipSuccess) {
     delete c;
     return PICS_ERR_HIP;
   }
@@ -592,6 +632,44 @@ int apply_A(pics_ctx* c, const void* x, void* y, int32_t terms) {
   }
   if (explicit_w) {
     // gam W^H W x through the wavelet kernels (coefficients in z, image in r)
+    TvArgs none{};
+    int rc = wavelet_analysis(c, (const float2*)x, 0, c->z, nullptr, nullptr, none);
+    if (rc) return rc;
+    rc = wavelet_synthesis(c, c->z, 0, c->r, nullptr, nullptr);
+    if (rc) return rc;
+    HIPCHK(c, launch_add_gamma(make_simple(c), make_ws(c), c->r, (const float2*)x, (float2*)y));
+  }
+  return PICS_OK;
+}
+
+int apply_A_noalloc(pics_ctx* c, const void* x, void* y, int32_t terms, int32_t coil_groups) {
+  if (!c) return PICS_ERR_INVALID;
+  if (!x || !y || x == y) return fail(c, PICS_ERR_INVALID, "apply_A_noalloc: null or aliased buffers");
+  if (terms < 0 || terms > (PICS_TERM_ALL | PICS_TERM_WAVELET_EXPLICIT))
+    return fail(c, PICS_ERR_INVALID, "apply_A_noalloc: terms %d", terms);
+  if (coil_groups < 1 || coil_groups > 64)
+    return fail(c, PICS_ERR_INVALID, "apply_A_noalloc: coil_groups %d outside 1..64", coil_groups);
+  int need = 1;
+  for (const auto& g : c->groups)
+    if (g.mask_kind == PICS_MASK_LINES) need = std::max(need, std::min((int)coil_groups, g.nc_max));
+  const unsigned long long bytes = need > 1 ? sizeof(float2) * (unsigned long long)c->img_total * need : 0ULL;
+  if (bytes > (unsigned long long)PICS_NOALLOC_SCRATCH_BYTES)
+    return fail(c, PICS_ERR_INVALID,
+                "apply_A_noalloc: a coil split of %d over %lld image elements needs %llu bytes of scratch, above "
+                "the %d-byte maximum (use fewer coil groups or fewer slices per context)",
+                need, c->img_total, bytes, (int)PICS_NOALLOC_SCRATCH_BYTES);
+  if (need > 1 && !c->scratch_dev) return fail(c, PICS_ERR_HIP, "apply_A_noalloc: scratch address not resolved");
+  const bool explicit_w = (terms & PICS_TERM_WAVELET_EXPLICIT) && (terms & PICS_TERM_GAMMA);
+  const int kterms = explicit_w ? (terms & (TERM_DATA | TERM_TV)) : (terms & TERM_ALL);
+  {
+    GroupFork fk(c);
+    for (auto& g : c->groups)
+      HIPCHK(c, launch_operator(c, g, CA_APPLY, kterms, c->pk, 0.0, (const float2*)x, nullptr, nullptr, nullptr,
+                                (float2*)y, std::min((int)coil_groups, std::max(1, g.nc_max)), c->scratch_dev));
+    HIPCHK(c, fk.join());
+  }
+  if (explicit_w) {
+    // gam W^H W x through the wavelet kernels, in the context's workspace
     TvArgs none{};
     int rc = wavelet_analysis(c, (const float2*)x, 0, c->z, nullptr, nullptr, none);
     if (rc) return rc;
