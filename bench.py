@@ -420,6 +420,35 @@ def param_sets_section(torch, B, nslices=8):
     return out
 
 
+def superoptimal_loss(data) -> float:
+    """Reporting: the loss floor of a per-instance diagonal d = H / G (each
+    instance's own per-frequency optimum), from the probe statistics."""
+    G = data.G.cpu().numpy().reshape(data.n, -1).astype(np.float64)
+    H = data.H.cpu().numpy().reshape(data.n, -1).astype(np.float64)
+    Z = data.Z.cpu().numpy().reshape(data.n, -1).astype(np.float64)
+    per = (Z - H * H / G).sum(axis=1) / Z.sum(axis=1)
+    return float(per.mean())
+
+
+def superoptimal_correction(torch, B, instance, nprobes: int = 32, probe_seed: int = 97_000):
+    """Reporting: probe estimate of the per-frequency optimum c* = G / (k H)
+    of the loss at the slice's own resolution (the ceiling of any spectrum
+    correction), from the library's spectrum and probe statistics."""
+    ctx, _ = B.context_for([instance])
+    s = instance.spec
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    probes = np.stack([gen.probe_vectors(probe_seed + p, 1, s.m, s.n)[0].ravel() for p in range(nprobes)])
+    pd = B.to_device(probes.astype(np.complex64).ravel())
+    G = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    H = torch.empty_like(G)
+    Z = torch.empty_like(G)
+    ctx.probe_stats(pd, nprobes, G, H, Z)
+    c = (G.double() / (khat.double() * H.double())).float()
+    ctx.close()
+    return c
+
+
 def learned_section(torch, B, steps):
     """Train the spectrum correction on 2000 instances of the 64 x 64 x 4
     training distribution (random R in [2, 8], mu / lambda / gamma within a
@@ -443,15 +472,15 @@ def learned_section(torch, B, steps):
     t_train = time.perf_counter() - t1
     learned = LD.dataset_loss(net, held)
     tr1 = LD.dataset_loss(net, train)
-    floor = LD.superoptimal_loss(held)
-    tfloor = LD.superoptimal_loss(train)
+    floor = superoptimal_loss(held)
+    tfloor = superoptimal_loss(train)
     inst = gen.make_instance(gen.CFG5, gen.eval_seed(5))
     sb = LD.evaluate_on(inst, net, n_outer=20)
     pcg = LD.pcg_first_solve(inst, net, curve=3)
     inst_s = gen.make_instance(gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1e3),
                                gen.eval_seed(5))
     sb_scaled = LD.evaluate_on(inst_s, net, n_outer=20)
-    ceiling = LD.evaluate_correction(inst, LD.superoptimal_correction(inst, nprobes=32))
+    ceiling = LD.evaluate_correction(inst, superoptimal_correction(torch, B, inst, nprobes=32))
     # harder operators at 256 x 256 x 12: parameter set 2 (mu = 1e-2, inside
     # the training range) and mu = 1e-1 (data term dominant, outside it); the
     # probe-estimated superoptimal diagonal bounds what any spectrum
@@ -460,7 +489,7 @@ def learned_section(torch, B, steps):
     for label, mu in (("mu_1e-2", 1e-2), ("mu_1e-1", 1e-1)):
         inst_h = gen.make_instance(gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, mu=mu, lam=4e-3,
                                                  gam=1e-3), gen.eval_seed(5))
-        ceil_h = LD.evaluate_correction(inst_h, LD.superoptimal_correction(inst_h, nprobes=32), n_outer=2)
+        ceil_h = LD.evaluate_correction(inst_h, superoptimal_correction(torch, B, inst_h, nprobes=32), n_outer=2)
         harder[label] = {"pcg_from_zero": LD.pcg_first_solve(inst_h, net, curve=3),
                          "superoptimal_probe_ceiling_iters_to_1e-3": ceil_h["pcg_iters_to_1e-3"]}
     for d in (train, held):

@@ -26,17 +26,20 @@
  *     pics_sizes() returns the packed totals.
  *   - every data pointer is a device pointer owned by the caller; sizes are
  *     element counts.  The context borrows `sens` and `masks` until
- *     pics_destroy() and owns its workspace.  The fixed part is allocated in
- *     pics_create.  Three grow-only tables are allocated, or enlarged, by the
- *     first call that needs them, and kept until pics_destroy:
- *       - the per-solve iteration history of split_bregman_recon
- *         (2 x n_outer n_inner x nslices int32);
- *       - the iteration-lock table (pcg_solve with maxit_per_slice,
- *         split_bregman_recon with lock_iters);
- *       - the coil-split partial sums, when pics_autotune or pics_set_option
- *         selects a split G > 1 (G x image-packed c64).
- *     Before it enlarges a table, such a call synchronises the stream.
- *     Repeated calls with the same sizes allocate nothing.
+ *     pics_destroy() and owns its workspace, allocated by pics_create and by
+ *     the set-up calls below; the calls that do the work (apply_A,
+ *     apply_Minv, pcg_solve, split_bregman_recon, ...) allocate nothing:
+ *       - the iteration-lock table and the per-solve history of
+ *         split_bregman_recon are sized for 64 solves (n_outer x n_inner) by
+ *         pics_create; pics_reserve enlarges them (a reconstruction with more
+ *         solves is refused with PICS_ERR_INVALID until then);
+ *       - the coil-split partial sums (G x image-packed c64) are allocated by
+ *         pics_autotune or pics_set_option when they choose a split G > 1
+ *         (apply_A_noalloc uses a static array instead).
+ *     A split_bregman_recon that replays outer iterations from a HIP graph
+ *     instantiates that graph on its first call with a given output buffer,
+ *     tolerance and preconditioner (the HIP runtime then sets up the graph's
+ *     resources); later calls with the same arguments replay it.
  *   - calls are ordered on the stream given at creation and asynchronous
  *     unless they return host results (those synchronise that stream).
  *     One host thread per context at a time; separate contexts (each on
@@ -112,6 +115,13 @@ int pics_destroy(pics_ctx* ctx);
 /* Packed element counts: image-shaped (c64 elements), coil-shaped (c64
  * elements) and mask bytes. */
 int pics_sizes(const pics_ctx* ctx, int64_t* image_elems, int64_t* coil_elems, int64_t* mask_bytes);
+
+/* Room for split_bregman_recon runs of up to max_solves = n_outer x n_inner
+ * solves (iteration-lock schedule and per-solve history, 3 x max_solves x
+ * nslices int32); pics_create reserves 64.  A set-up call: it synchronises
+ * the stream and allocates when max_solves exceeds the current room, and does
+ * nothing otherwise.  PICS_ERR_INVALID outside 1 .. 2^20. */
+int pics_reserve(pics_ctx* ctx, int32_t max_solves);
 
 /* Build the preconditioner (paper, Efficient Implementation of the
  * Preconditioner, Eqs. d and diagonalelements; Table 1 lists its cost):

@@ -61,6 +61,7 @@ def signatures():
         "pics_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(Desc), vp, vp, vp]),
         "pics_destroy": (ctypes.c_int, [vp]),
         "pics_sizes": (ctypes.c_int, [vp, pi64, pi64, pi64]),
+        "pics_reserve": (ctypes.c_int, [vp, i32]),
         "build_preconditioner": (ctypes.c_int, [vp, i32, vp, vp]),
         "apply_A": (ctypes.c_int, [vp, vp, vp, i32]),
         "apply_A_noalloc": (ctypes.c_int, [vp, vp, vp, i32, i32]),
@@ -180,6 +181,10 @@ class Context:
 
     def set_option(self, key: int, value: int):
         return self._check(self.L.pics_set_option(self.h, key, value))
+
+    def reserve(self, max_solves: int):
+        """Room for Split Bregman runs of up to max_solves solves (64 by default)."""
+        return self._check(self.L.pics_reserve(self.h, int(max_solves)))
 
     def autotune(self, flags: int = 0):
         """Time the coil splits of the fused operator per size group and keep

@@ -57,9 +57,13 @@ struct pics_ctx {
   double *part, *pbar;
   PcgState* st = nullptr;
   int* bad = nullptr;
-  int* lock_dev = nullptr;
-  int lock_cap = 0;  // ints available at lock_dev (grown on demand by split_bregman_recon)
-  void* lock_block = nullptr;
+  // iteration-lock schedule and per-solve history, sized for `solves_cap`
+  // solves: inside `block` as created, in `reserve_block` once pics_reserve
+  // has enlarged them
+  long long solves_cap = 0;
+  int* lock_dev = nullptr;       // [solves_cap][nslices]
+  long long lock_cap = 0;        // ints at lock_dev
+  void* reserve_block = nullptr;
 
   PcgState* st_host = nullptr;  // pinned
   int* flag_host = nullptr;      // pinned
@@ -71,7 +75,7 @@ struct pics_ctx {
   int graph_budget = 1;          // PCG iterations per solve inside the graph (0: host-polled only)
   int* solve_counter = nullptr;  // device: history row of the next solve
   int* hist = nullptr;           // device: [solves][nslices] iterations, then [solves][nslices] status
-  long long hist_cap = 0;
+  long long hist_cap = 0;        // ints at hist (2 solves_cap nslices)
   std::vector<int> hist_host;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -112,6 +116,7 @@ static __device__ __align__(256) float2 scratch[PICS_NOALLOC_SCRATCH_BYTES / siz
 namespace {
 
 constexpr int kMaxDevices = 64;
+constexpr long long kDefaultSolves = 64;  // solves per reconstruction reserved by pics_create
 std::mutex g_scratch_mu;
 float2* g_scratch_addr[kMaxDevices] = {};
 
@@ -379,6 +384,29 @@ int pics_sizes(const pics_ctx* c, int64_t* img, int64_t* coil, int64_t* mask) {
   return PICS_OK;
 }
 
+int pics_reserve(pics_ctx* c, int32_t max_solves) {
+  if (!c) return PICS_ERR_INVALID;
+  if (max_solves < 1 || max_solves > (1 << 20)) return fail(c, PICS_ERR_INVALID, "pics_reserve: max_solves %d", max_solves);
+  if (max_solves <= c->solves_cap) return PICS_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const size_t lock_bytes = (sizeof(int) * (size_t)max_solves * c->nslices + 255) / 256 * 256;
+  const size_t hist_bytes = sizeof(int) * 2 * (size_t)max_solves * c->nslices;
+  void* blk = nullptr;
+  HIPCHK(c, hipMalloc(&blk, lock_bytes + hist_bytes));
+  if (c->graph_exec) {  // the graph records the old history's address
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+  if (c->reserve_block) (void)hipFree(c->reserve_block);
+  c->reserve_block = blk;
+  c->solves_cap = max_solves;
+  c->lock_dev = (int*)blk;
+  c->lock_cap = (long long)max_solves * c->nslices;
+  c->hist = (int*)((char*)blk + lock_bytes);
+  c->hist_cap = 2LL * max_solves * c->nslices;
+  return PICS_OK;
+}
+
 int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const void* sens, const uint8_t* masks,
                 void* stream) {
   if (!out) return PICS_ERR_INVALID;
@@ -471,6 +499,11 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
   add((void**)&c->st, sizeof(PcgState) * nslices);
   add((void**)&c->bad, sizeof(int));
   add((void**)&c->solve_counter, sizeof(int));
+  c->solves_cap = kDefaultSolves;
+  c->lock_cap = kDefaultSolves * nslices;
+  c->hist_cap = 2LL * kDefaultSolves * nslices;
+  add((void**)&c->lock_dev, sizeof(int) * c->lock_cap);
+  add((void**)&c->hist, sizeof(int) * c->hist_cap);
   size_t total = 0;
   for (auto& pr : plan) total += pr.second;
   if (hipMalloc(&c->block, total) != hipSuccess) {
@@ -532,12 +565,11 @@ int pics_destroy(pics_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  if (c->hist) (void)hipFree(c->hist);
+  if (c->reserve_block) (void)hipFree(c->reserve_block);
   if (c->dpart) (void)hipFree(c->dpart);
   for (auto st : c->side) (void)hipStreamDestroy(st);
   for (auto ev : c->side_done) (void)hipEventDestroy(ev);
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
-  if (c->lock_block) (void)hipFree(c->lock_block);
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->flag_host) (void)hipHostFree(c->flag_host);
   if (c->block) (void)hipFree(c->block);
@@ -824,29 +856,12 @@ int pcg_run(pics_ctx* c, const float2* b, float2* x, double tol, int maxit, cons
   return pcg_status_rc(c, tol);
 }
 
-int ensure_lock(pics_ctx* c, long long count) {
-  if (count <= c->lock_cap) return PICS_OK;
-  if (c->lock_block) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipFree(c->lock_block));
-    c->lock_block = nullptr;
-    c->lock_cap = 0;
-  }
-  HIPCHK(c, hipMalloc(&c->lock_block, sizeof(int) * count));
-  c->lock_dev = (int*)c->lock_block;
-  c->lock_cap = (int)count;
-  return PICS_OK;
-}
-
-int ensure_hist(pics_ctx* c, long long solves) {
-  const long long need = 2 * solves * c->nslices;
-  if (need <= c->hist_cap) return PICS_OK;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (c->hist) HIPCHK(c, hipFree(c->hist));
-  c->hist = nullptr;
-  HIPCHK(c, hipMalloc((void**)&c->hist, sizeof(int) * need));
-  c->hist_cap = need;
-  return PICS_OK;
+// The lock schedule and history are sized by pics_create and pics_reserve;
+// hot calls only check that the request fits (they never allocate).
+int check_solves(pics_ctx* c, const char* who, long long solves) {
+  if (solves <= c->solves_cap) return PICS_OK;
+  return fail(c, PICS_ERR_INVALID, "%s: %lld solves exceed the %lld reserved for this context (pics_reserve)", who,
+              solves, c->solves_cap);
 }
 
 // Split Bregman step 4: b = g_j + lam [D_x^H u_x + D_y^H u_y] + gam W^H u_w
@@ -956,8 +971,6 @@ int pcg_solve(pics_ctx* c, const void* b, void* x, double tol, int32_t maxit, co
       if (maxit_per_slice[s] < 0) return fail(c, PICS_ERR_INVALID, "pcg_solve: maxit_per_slice");
       maxit_max = std::max(maxit_max, (int)maxit_per_slice[s]);
     }
-    int rc = ensure_lock(c, c->nslices);
-    if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(c->lock_dev, maxit_per_slice, sizeof(int) * c->nslices, hipMemcpyHostToDevice,
                              c->stream));
     mdev = c->lock_dev;
@@ -981,18 +994,16 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
     if (!(c->desc[s].lambda > 0.0) || !(c->desc[s].gamma > 0.0))
       return fail(c, PICS_ERR_INVALID, "split_bregman_recon: lambda and gamma must be > 0 (shrink thresholds)");
   const long long nsolve = (long long)n_outer * n_inner;
-  if (lock_iters) {
-    int rc = ensure_lock(c, std::max(1LL, nsolve * c->nslices));
+  if (nsolve > 0) {
+    const int rc = check_solves(c, "split_bregman_recon", nsolve);
     if (rc) return rc;
+  }
+  if (lock_iters) {
     HIPCHK(c, hipMemcpyAsync(c->lock_dev, lock_iters, sizeof(int) * nsolve * c->nslices, hipMemcpyHostToDevice,
                              c->stream));
   }
   float2* x = (float2*)x_out;
   const bool use_graph = !lock_iters && c->graph_budget > 0 && n_outer > 1 && tol > 0.0;
-  if (use_graph) {
-    int rc = ensure_hist(c, nsolve);
-    if (rc) return rc;
-  }
   for (int attempt = 0; attempt < 2; ++attempt) {
     const bool graph_now = use_graph && attempt == 0;
     // Algorithm 1, step 1: coil images F^H R y_i, root sum of squares, g_1

@@ -62,15 +62,6 @@ def dataset_loss(net: "B.Net", data: Dataset, batch: int = 16) -> float:
     return total / data.n
 
 
-def superoptimal_loss(data: Dataset) -> float:
-    """Loss floor of a per-instance diagonal d = H / G (reporting only)."""
-    G = data.G.cpu().numpy().reshape(data.n, -1).astype(np.float64)
-    H = data.H.cpu().numpy().reshape(data.n, -1).astype(np.float64)
-    Z = data.Z.cpu().numpy().reshape(data.n, -1).astype(np.float64)
-    per = (Z - H * H / G).sum(axis=1) / Z.sum(axis=1)
-    return float(per.mean())
-
-
 def train(net: "B.Net", data: Dataset, steps: int, batch: int = 16, lr: float = 1e-3, seed: int = 1234,
           log_every: int = 0, log=print) -> List[float]:
     import torch
@@ -158,25 +149,6 @@ def pcg_first_solve(instance, net: Optional["B.Net"], curve: int = 3) -> dict:
         out[kind] = {"iters_to_1e-3": int(it[0]), "relres_curve": relres_curve(ctx, b, x0, curve)}
     ctx.close()
     return out
-
-
-def superoptimal_correction(instance, nprobes: int = 32, probe_seed: int = 97_000):
-    """Probe estimate of the per-frequency optimum c* = G / (k H) of the loss
-    at the slice's own resolution (the ceiling of any spectrum correction)."""
-    import torch
-    ctx, _ = B.context_for([instance])
-    s = instance.spec
-    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
-    ctx.build_preconditioner("circulant", khat=khat)
-    probes = np.stack([gen.probe_vectors(probe_seed + p, 1, s.m, s.n)[0].ravel() for p in range(nprobes)])
-    pd = B.to_device(probes.astype(np.complex64).ravel())
-    G = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
-    H = torch.empty_like(G)
-    Z = torch.empty_like(G)
-    ctx.probe_stats(pd, nprobes, G, H, Z)
-    c = (G.double() / (khat.double() * H.double())).float()
-    ctx.close()
-    return c
 
 
 def evaluate_correction(instance, corr, n_outer: int = 20, curve: int = 3) -> dict:

@@ -204,3 +204,47 @@ def test_zero_operator_is_a_breakdown(torch, B):
     rc, iters, st = _raw_pcg(B, ctx, b, x, 1e-3, 100)
     assert rc == B.PICS_ERR_BREAKDOWN and st[0] == B.PICS_ERR_BREAKDOWN, (rc, st)
     assert np.all(np.isfinite(_host(x)))
+
+
+def test_hot_calls_allocate_nothing(torch, B):
+    """After creation and set-up, the working calls leave the device's free
+    memory unchanged when repeated; a reconstruction with more solves than the
+    context has room for is refused (not grown on demand) until pics_reserve
+    makes room."""
+    _say("edge: hot calls allocate nothing")
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1e3)
+    insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(2)]
+    ctx, ksp = B.context_for(insts)
+    ctx.build_preconditioner("circulant")
+    xa = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    ya = torch.empty_like(xa)
+    x = torch.zeros_like(xa)
+    lock = np.full((20, 2), 2, np.int32)
+
+    def work():
+        ctx.apply_A(xa, ya)
+        ctx.apply_Minv(xa, ya)
+        x.zero_()
+        ctx.pcg_solve(xa, x, 1e-3, 100)
+        x.zero_()
+        ctx.pcg_solve(xa, x, 0.0, 0, maxit_per_slice=[3, 2])
+        x.zero_()
+        ctx.split_bregman_recon(ksp, x, n_outer=20, tol=1e-3, maxit=1000)
+        x.zero_()
+        ctx.split_bregman_recon(ksp, x, n_outer=20, lock=lock)
+        torch.cuda.synchronize()
+
+    work()  # first replay-graph instantiation happens here
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(3):
+        work()
+    free1 = torch.cuda.mem_get_info()[0]
+    _say(f"  free device memory before / after three more rounds: {free0} / {free1}")
+    assert free1 == free0
+    with pytest.raises(B.PicsError) as e:
+        ctx.split_bregman_recon(ksp, x, n_outer=65, tol=1e-3, maxit=1000)
+    assert e.value.code == B.PICS_ERR_INVALID and "pics_reserve" in str(e.value)
+    ctx.reserve(65)
+    it65, _ = ctx.split_bregman_recon(ksp, x, n_outer=65, tol=1e-3, maxit=1000)
+    assert it65.shape == (65, 2) and np.all(it65 >= 0)
+    ctx.close()
