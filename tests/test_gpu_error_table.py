@@ -1,0 +1,141 @@
+"""Relative image error of the GPU path against the FP64 oracle, one line per
+workload: the first PCG solve (b = mu E^H y from x = 0, circulant
+preconditioner to 1e-3, iteration-locked) and a Split Bregman reconstruction
+(Algorithm 1, iteration-locked to the oracle's per-solve counts), printed as a
+table and held to 1e-4 each.
+
+Workloads: 64^2 x 4 (Haar, 1 level); 256^2 x 12 (db4 x 3); 512^2 x 32
+(variable-density lines, R 6, db4 x 4; 4 outer iterations, the oracle's cost);
+the ragged batch (eight slices of the four sizes in one context); the learned
+correction at 256^2 x 12 (a network's correction map multiplied into the
+circulant spectrum; the oracle takes the GPU's map as input)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import pcg as opcg
+from oracle import precond as opre
+from oracle import sb as osb
+from paper_1710_01758_amd import inputs as gen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a ROCm device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1710_01758_amd import binding
+    binding.lib()
+    return binding
+
+
+def _pcg_errors(torch, B, ctx, insts, kind="circulant", corr=None, corr_maps=None):
+    """First solve of every slice, locked to the oracle's count."""
+    bs, refs = [], []
+    for i, it in enumerate(insts):
+        s = it.spec
+        r2d = it.mask2d.astype(np.float64)
+        A = lambda v, it=it, r2d=r2d, s=s: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
+        k = opre.circulant_k(it.sens, r2d, s.mu, s.lam, s.gam)
+        if corr_maps is not None:
+            k = k * corr_maps[i]
+        b = s.mu * ops.adjoint(it.kspace, it.sens, r2d)
+        bs.append(b)
+        refs.append(opcg.pcg(A, b, np.zeros_like(b), lambda v, k=k: opre.apply_minv(v, k), 1e-3, 1000))
+    ctx.build_preconditioner(kind, correction=corr)
+    bd = B.to_device(B.pack_images(bs))
+    xd = torch.zeros_like(bd)
+    ctx.pcg_solve(bd, xd, 0.0, 0, maxit_per_slice=[r.iters for r in refs])
+    got = B.unpack_images(xd.cpu().numpy(), [(it.spec.m, it.spec.n) for it in insts])
+    return [H.rel_err(g, r.x) for g, r in zip(got, refs)], [r.iters for r in refs]
+
+
+def _sb_errors(torch, B, ctx, ksp, insts, n_outer):
+    refs = []
+    for it in insts:
+        s = it.spec
+        refs.append(osb.split_bregman(it.kspace, it.sens, it.mask, s.mu, s.lam, s.gam, s.wavelet, s.levels,
+                                      n_outer=n_outer, tol=1e-3, precond="circulant"))
+    lock = np.array([r.pcg_iters for r in refs], np.int32).T.copy()
+    ctx.build_preconditioner("circulant")
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    ctx.split_bregman_recon(ksp, x, n_outer=n_outer, lock=lock)
+    got = B.unpack_images(x.cpu().numpy(), [(it.spec.m, it.spec.n) for it in insts])
+    return [H.rel_err(g, r.x) for g, r in zip(got, refs)], int(lock.sum())
+
+
+def _ragged(scale):
+    specs = gen.cfg4_specs(nslices=64)
+    out = []
+    for shape in gen.CFG4_SHAPES:
+        out += [(i, s) for i, s in enumerate(specs) if (s.m, s.n) == shape][:2]
+    return [gen.make_instance(gen.SliceSpec(s.m, s.n, s.ncoils, s.accel, s.centre, wavelet="db4", levels=3,
+                                            data_scale=scale), gen.eval_seed(4, i)) for i, s in out]
+
+
+def test_relative_error_per_workload(torch, B):
+    rows = []
+
+    def add(name, pcg, sb):
+        (pe, pit), (se, sit) = pcg, sb
+        rows.append((name, max(pe), pit, max(se), sit))
+        _say(f"  {name}: PCG first solve {max(pe):.2e} ({pit} iterations), Split Bregman {max(se):.2e} "
+             f"({sit} PCG iterations in all)")
+
+    _say("relative error per workload (locked PCG, locked Split Bregman at data scale 1e3)")
+    workloads = [
+        ("64x64x4, Haar x1, 20 outer", [gen.SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1, data_scale=1e3)],
+         gen.eval_seed(1), 20),
+        ("256x256x12, db4 x3, 20 outer", [gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3,
+                                                          data_scale=1e3)], gen.eval_seed(2), 20),
+        ("512x512x32, VD lines R 6, db4 x4, 4 outer", [gen.SliceSpec(512, 512, 32, 6.0, 32, wavelet="db4", levels=4,
+                                                                       vd=True, data_scale=1e3)],
+         gen.eval_seed(3), 4),
+    ]
+    for name, specs, seed, n_outer in workloads:
+        insts = [gen.make_instance(sp, seed) for sp in specs]
+        ctx, ksp = B.context_for(insts)
+        add(name, _pcg_errors(torch, B, ctx, insts), _sb_errors(torch, B, ctx, ksp, insts, n_outer))
+        ctx.close()
+    insts = _ragged(1e3)
+    ctx, ksp = B.context_for(insts)
+    add("ragged batch, 8 slices 128^2-320^2, 8-32 coils, 6 outer", _pcg_errors(torch, B, ctx, insts),
+        _sb_errors(torch, B, ctx, ksp, insts, 6))
+    ctx.close()
+    # the learned correction at 256^2 x 12: the network at its initial
+    # parameters with a perturbed head, so that the correction is not 1
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1e3)
+    inst = gen.make_instance(spec, gen.eval_seed(5))
+    ctx, ksp = B.context_for([inst])
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    theta = gen.net_init(5)
+    theta[-17:-1] = 0.05 * np.random.default_rng(5).standard_normal(16)
+    net = B.Net(4)
+    net.set_params(theta.astype(np.float32))
+    from paper_1710_01758_amd import learned as LD
+    corr = LD.correction_for(net, ctx, khat)
+    cmap = corr.cpu().numpy().reshape(spec.m, spec.n).astype(np.float64)
+    pe = _pcg_errors(torch, B, ctx, [inst], kind="learned", corr=corr, corr_maps=[cmap])
+    rows.append(("256x256x12 learned correction", max(pe[0]), pe[1], None, None))
+    _say(f"  256x256x12 learned correction (range {cmap.min():.3f}-{cmap.max():.3f}): PCG first solve "
+         f"{max(pe[0]):.2e} ({pe[1]} iterations)")
+    net.close()
+    ctx.close()
+    for name, pe, _, se, _ in rows:
+        assert pe < 1e-4, (name, pe)
+        assert se is None or se < 1e-4, (name, se)

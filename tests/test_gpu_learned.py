@@ -112,13 +112,19 @@ def test_forward_loss_and_gradient_match_oracle(torch, B, small_data):
     L_ref, g_ref = OL.loss_and_grad(theta32, feats, kk, GG, HH, ZZ)
     _say(f"  loss gpu {loss:.6e} oracle {L_ref:.6e}; grad rel err {H.rel_err(g_gpu, g_ref):.3e}")
     assert abs(loss - L_ref) < 2e-2 * abs(L_ref)
-    assert H.rel_err(g_gpu, g_ref) < 5e-2
-    # per-layer check (every layer's block of the gradient)
-    off = 0
+    assert H.rel_err(g_gpu, g_ref) < 2e-2
+    # per-layer check (every layer's block of the gradient, then the head)
+    off, errs = 0, []
     for ci, co, _ in OL.LAYERS:
         nW = co * ci * 9 + co
-        assert H.rel_err(g_gpu[off:off + nW], g_ref[off:off + nW]) < 8e-2, off
+        errs.append(H.rel_err(g_gpu[off:off + nW], g_ref[off:off + nW]))
         off += nW
+    errs.append(H.rel_err(g_gpu[off:], g_ref[off:]))
+    _say("  per-layer gradient rel err " + " ".join(f"{e:.2e}" for e in errs))
+    # the first layers' blocks carry the BF16 rounding of the gradient maps
+    # of every layer above them (measured 2.9e-2 for the first, 5e-3 for the
+    # head); the whole gradient stays within 2e-2
+    assert max(errs) < 4e-2, errs
     net.close()
 
 
@@ -165,6 +171,13 @@ def test_learned_fallback_on_bad_correction(torch, B):
     assert float(khat.min()) > 0
 
 
+def _superoptimal_floor(data):
+    """Mean over instances of the per-frequency optimum of the loss,
+    sum(Z - H^2 / G) / sum(Z), from the probe statistics."""
+    G, Hs, Z = (a.cpu().numpy().reshape(data.n, -1).astype(np.float64) for a in (data.G, data.H, data.Z))
+    return float(((Z - Hs * Hs / G).sum(axis=1) / Z.sum(axis=1)).mean())
+
+
 def test_training_lowers_heldout_loss_below_circulant(torch, B, LD):
     _say("learned: short training")
     train = LD.build_dataset(gen.training_instances(160, base=gen.TRAIN_SEED_BASE), nprobes=8)
@@ -174,9 +187,52 @@ def test_training_lowers_heldout_loss_below_circulant(torch, B, LD):
     circ = LD.dataset_loss(net, held)      # c = 1: the circulant preconditioner
     losses = LD.train(net, train, steps=300, batch=16, lr=1e-3)
     learned = LD.dataset_loss(net, held)
-    floor = LD.superoptimal_loss(held)
+    floor = _superoptimal_floor(held)
     _say(f"  held-out loss: circulant {circ:.6f} learned {learned:.6f} superoptimal floor {floor:.6f}; "
          f"train first {np.mean(losses[:20]):.6f} last {np.mean(losses[-20:]):.6f}")
     assert learned < circ
     assert learned >= floor * (1 - 1e-3)
+    net.close()
+
+
+def test_trained_correction_saves_an_iteration_where_the_circulant_is_weak(torch, B, LD):
+    """The benchmark's training recipe (2000 training instances of the 64 x 64
+    x 4 distribution, 1500 Adam steps of 16, learning rate 1e-3), then a
+    256 x 256 x 12 slice whose data term dominates (mu = 1e-1, lambda = 4e-3,
+    gamma = 1e-3, outside the training range): PCG from 0 on A x = A x_true
+    needs fewer iterations to 1e-3 with the learned spectrum than with the
+    circulant one.  Both counts equal the FP64 oracle's for the same spectra
+    (the oracle takes the GPU's correction map as an input)."""
+    _say("learned: fewer PCG iterations than circulant at mu = 1e-1")
+    train = LD.build_dataset(gen.training_instances(2000, base=gen.TRAIN_SEED_BASE), nprobes=8)
+    net = B.Net(16)
+    net.set_params(gen.net_init(20_260).astype(np.float32))
+    LD.train(net, train, steps=1500, batch=16, lr=1e-3)
+    train.ctx.close()
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, mu=1e-1, lam=4e-3, gam=1e-3)
+    inst = gen.make_instance(spec, gen.eval_seed(5))
+    ctx, _ = B.context_for([inst])
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    corr = LD.correction_for(net, ctx, khat)
+    c_gpu = corr.cpu().numpy().reshape(spec.m, spec.n).astype(np.float64)
+    r2d = inst.mask2d.astype(np.float64)
+    A = lambda v: ops.apply_A(v, inst.sens, r2d, spec.mu, spec.lam, spec.gam)
+    b = A(inst.x_true)
+    k = opre.circulant_k(inst.sens, r2d, spec.mu, spec.lam, spec.gam)
+    bd = B.to_device(b.astype(np.complex64).ravel())
+    counts = {}
+    for kind, kk in (("circulant", k), ("learned", k * c_gpu)):
+        ref = opcg.pcg(A, b, np.zeros_like(b), lambda v, kk=kk: opre.apply_minv(v, kk), 1e-3, 100)
+        ctx.build_preconditioner(kind, correction=corr if kind == "learned" else None)
+        xd = torch.zeros_like(bd)
+        it, _, st, _ = ctx.pcg_solve(bd, xd, 1e-3, 100)
+        counts[kind] = (int(it[0]), ref.iters)
+        assert st[0] == 1
+        assert int(it[0]) == ref.iters, (kind, int(it[0]), ref.iters)
+    _say(f"  iterations to 1e-3 (GPU, oracle): circulant {counts['circulant']}, learned {counts['learned']}; "
+         f"correction range [{c_gpu.min():.4f}, {c_gpu.max():.4f}]")
+    assert counts["learned"][0] < counts["circulant"][0]
+    assert counts["learned"][1] < counts["circulant"][1]
+    ctx.close()
     net.close()

@@ -131,7 +131,7 @@ def test_2d_split_bregman_locked(torch, B, scale):
     iters, _ = ctx.split_bregman_recon(ksp, x, n_outer=8, tol=1e-3, maxit=1000, lock=ref.pcg_iters)
     err = H.rel_err(_host(x).reshape(spec.m, spec.n), ref.x)
     _say(f"  locked rel err {err:.2e}")
-    assert err < 1e-3
+    assert err < 1e-4
     x.zero_()
     it_free, _ = ctx.split_bregman_recon(ksp, x, n_outer=8, tol=1e-3, maxit=1000)
     assert max(abs(int(a) - int(b)) for a, b in zip(it_free[:, 0], ref.pcg_iters)) <= 1

@@ -1,7 +1,7 @@
 """GPU parity: the native HIP path (through the C ABI) against the FP64 oracle
 on the same seeded inputs.  Tolerances: FFT / apply_A / k / M^{-1} / wavelets
 1e-5 relative; PCG iteration-locked 1e-4 relative (complex64 vectors with
-FP64 reductions); Split Bregman iteration-locked 1e-3."""
+FP64 reductions); Split Bregman iteration-locked 1e-4."""
 import sys
 
 import numpy as np
@@ -296,7 +296,7 @@ def test_split_bregman_cfg1_locked(torch, B, scale):
     assert np.array_equal(iters[:, 0], lock[:, 0])
     err = H.rel_err(_host(xd).reshape(spec.m, spec.n), ref.x)
     _say(f"  sb cfg1 scale {scale}: rel err vs oracle {err:.3e}, iters {ref.pcg_iters}")
-    assert err < 1e-3, err
+    assert err < 1e-4, err
     # free-running counts stay within one of the oracle's per solve
     xd.zero_()
     free, rc = ctx.split_bregman_recon(ksp, xd, n_outer=20, tol=1e-3, maxit=1000)
@@ -316,7 +316,7 @@ def test_split_bregman_cfg2_locked(torch, B):
     ctx.split_bregman_recon(ksp, xd, n_outer=6, lock=lock)
     err = H.rel_err(_host(xd).reshape(spec.m, spec.n), ref.x)
     _say(f"  sb cfg2: rel err vs oracle {err:.3e}")
-    assert err < 1e-3, err
+    assert err < 1e-4, err
 
 
 def _sb_run(torch, B, insts, budget, n_outer=8, scale_note=""):
@@ -429,7 +429,7 @@ def test_split_bregman_coil_split_graph(torch, B):
     assert np.array_equal(itp, itg)
     assert np.array_equal(xp, xg)
     x1, _ = run(1, 0, lock=itp)
-    assert H.rel_err(xp, x1) < 1e-3, H.rel_err(xp, x1)
+    assert H.rel_err(xp, x1) < 1e-4, H.rel_err(xp, x1)
 
 
 def test_autotune_picks_a_valid_split(torch, B, tmp_path, monkeypatch):
@@ -565,7 +565,7 @@ def test_split_bregman_tv_only_and_mixed_batch(torch, B):
     for s, r in enumerate(refs):
         err = H.rel_err(got[s], r.x)
         _say(f"  slice {s} ({specs[s].wavelet}): rel err vs oracle {err:.2e}")
-        assert err < 1e-3, (s, err)
+        assert err < 1e-4, (s, err)
     x.zero_()
     free, rc = ctx.split_bregman_recon(ksp, x, n_outer=8, tol=1e-3, maxit=1000)
     assert np.all(np.abs(free - lock) <= 1), (free, lock)
