@@ -64,32 +64,164 @@ template <> struct Split<32> { static constexpr int P = 8, Q = 4; };
 template <> struct Split<40> { static constexpr int P = 8, Q = 5; };
 template <> struct Split<64> { static constexpr int P = 8, Q = 8; };
 
+// Odd multiples of 45 degrees: exp(DIR 2 pi i K / R) = h (c + i DIR s) with
+// c, s = +-1 and h = 1/sqrt(2).  tw45_unscaled returns a (c + i DIR s)
+// (adds only); the caller owes the factor h, which the second-level DFT
+// below folds into fused multiply-adds.
+template <int R, int K>
+struct Tw45 {
+  static constexpr int k = ((K % R) + R) % R;
+  static constexpr bool value = k != 0 && (8 * k) % R == 0 && (((8 * k) / R) & 1) == 1;
+};
+template <int R, int K, int DIR>
+__device__ __forceinline__ float2 tw45_unscaled(float2 a) {
+  constexpr int oct = (8 * Tw45<R, K>::k) / R;  // 1, 3, 5 or 7
+  constexpr float c = (oct == 1 || oct == 7) ? 1.f : -1.f;
+  constexpr float sd = ((oct == 1 || oct == 3) ? 1.f : -1.f) * float(DIR);
+  return make_float2(c * a.x - sd * a.y, c * a.y + sd * a.x);
+}
+
+constexpr float kH = 0.70710678118654752440f;
+
+__device__ __forceinline__ float2 cfma(float s, float2 a, float2 b) {  // s a + b
+  return make_float2(__builtin_fmaf(s, a.x, b.x), __builtin_fmaf(s, a.y, b.y));
+}
+
+template <int R, int DIR>
+struct Dft;
+
+// DFT of Q points whose inputs flagged in SM (bit n) still owe a factor h.
+// The two patterns the radix-4 and radix-2 second levels meet (c2 alone; c1
+// and c3 together) fold h into fused multiply-adds; any other pattern
+// multiplies first.
+template <int Q, int DIR, int SM>
+struct DftScaled {
+  static __device__ __forceinline__ void run(float2 (&c)[Q]) {
+#pragma unroll
+    for (int n = 0; n < Q; ++n)
+      if ((SM >> n) & 1) c[n] = cscale(c[n], kH);
+    Dft<Q, DIR>::run(c);
+  }
+};
+template <int DIR>
+struct DftScaled<2, DIR, 2> {
+  static __device__ __forceinline__ void run(float2 (&c)[2]) {
+    const float2 t = c[0];
+    c[0] = cfma(kH, c[1], t);
+    c[1] = cfma(-kH, c[1], t);
+  }
+};
+template <int DIR>
+struct DftScaled<4, DIR, 4> {  // c2 owes h
+  static __device__ __forceinline__ void run(float2 (&a)[4]) {
+    const float2 s02 = cfma(kH, a[2], a[0]), d02 = cfma(-kH, a[2], a[0]);
+    const float2 s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
+    const float2 j13 = cmul_i(d13, float(DIR));
+    a[0] = cadd(s02, s13);
+    a[2] = csub(s02, s13);
+    a[1] = cadd(d02, j13);
+    a[3] = csub(d02, j13);
+  }
+};
+template <int DIR>
+struct DftScaled<4, DIR, 10> {  // c1 and c3 owe h
+  static __device__ __forceinline__ void run(float2 (&a)[4]) {
+    const float2 s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+    const float2 u = cadd(a[1], a[3]), v = csub(a[1], a[3]);
+    const float2 jv = cmul_i(v, float(DIR));
+    a[0] = cfma(kH, u, s02);
+    a[2] = cfma(-kH, u, s02);
+    a[1] = cfma(kH, jv, d02);
+    a[3] = cfma(-kH, jv, d02);
+  }
+};
+
+// DFT of P points of the inputs s[n] a[n] (real scales, e.g. a sampling
+// mask): radix 4 folds the scales into fused multiply-adds.
+template <int P, int DIR>
+struct DftInScaled {
+  static __device__ __forceinline__ void run(float2 (&a)[P], const float (&s)[P]) {
+#pragma unroll
+    for (int n = 0; n < P; ++n) a[n] = cscale(a[n], s[n]);
+    Dft<P, DIR>::run(a);
+  }
+};
+template <int DIR>
+struct DftInScaled<4, DIR> {
+  static __device__ __forceinline__ void run(float2 (&a)[4], const float (&s)[4]) {
+    const float2 t0 = cscale(a[0], s[0]), t1 = cscale(a[1], s[1]);
+    const float2 s02 = cfma(s[2], a[2], t0), d02 = cfma(-s[2], a[2], t0);
+    const float2 s13 = cfma(s[3], a[3], t1), d13 = cfma(-s[3], a[3], t1);
+    const float2 j13 = cmul_i(d13, float(DIR));
+    a[0] = cadd(s02, s13);
+    a[2] = csub(s02, s13);
+    a[1] = cadd(d02, j13);
+    a[3] = csub(d02, j13);
+  }
+};
+
 template <int R, int DIR>
 struct Dft {
-  // composite: n = Q n1 + n2, k = k1 + P k2
+  // composite: n = Q n1 + n2, k = k1 + P k2; the inter-level twiddles that
+  // are odd multiples of 45 degrees leave their factor h to the second level
   static __device__ __forceinline__ void run(float2 (&a)[R]) {
     constexpr int P = Split<R>::P, Q = Split<R>::Q;
     float2 Y[Q][P];
-    static_for<0, Q>([&](auto n2c) {
-      constexpr int n2 = decltype(n2c)::value;
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
       float2 b[P];
 #pragma unroll
       for (int n1 = 0; n1 < P; ++n1) b[n1] = a[Q * n1 + n2];
       Dft<P, DIR>::run(b);
-      static_for<0, P>([&](auto k1c) {
-        constexpr int k1 = decltype(k1c)::value;
-        Y[n2][k1] = tw_mul<R, n2 * k1, DIR>(b[k1]);
-      });
-    });
 #pragma unroll
-    for (int k1 = 0; k1 < P; ++k1) {
+      for (int k1 = 0; k1 < P; ++k1) Y[n2][k1] = b[k1];
+    }
+    second_level(Y, a);
+  }
+  // the DFT of s[n] a[n] (real per-input scales)
+  static __device__ __forceinline__ void run_in_scaled(float2 (&a)[R], const float (&sc)[R]) {
+    constexpr int P = Split<R>::P, Q = Split<R>::Q;
+    float2 Y[Q][P];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
+      float2 b[P];
+      float sb[P];
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) {
+        b[n1] = a[Q * n1 + n2];
+        sb[n1] = sc[Q * n1 + n2];
+      }
+      DftInScaled<P, DIR>::run(b, sb);
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1) Y[n2][k1] = b[k1];
+    }
+    second_level(Y, a);
+  }
+  static __device__ __forceinline__ void second_level(float2 (&Y)[Split<R>::Q][Split<R>::P], float2 (&a)[R]) {
+    constexpr int P = Split<R>::P, Q = Split<R>::Q;
+    static_for<0, P>([&](auto k1c) {
+      constexpr int k1 = decltype(k1c)::value;
       float2 c[Q];
-#pragma unroll
-      for (int n2 = 0; n2 < Q; ++n2) c[n2] = Y[n2][k1];
-      Dft<Q, DIR>::run(c);
+      static_for<0, Q>([&](auto n2c) {
+        constexpr int n2 = decltype(n2c)::value;
+        if constexpr (Tw45<R, n2 * k1>::value)
+          c[n2] = tw45_unscaled<R, n2 * k1, DIR>(Y[n2][k1]);
+        else
+          c[n2] = tw_mul<R, n2 * k1, DIR>(Y[n2][k1]);
+      });
+      DftScaled<Q, DIR, scaled_mask<R, Q, k1>()>::run(c);
 #pragma unroll
       for (int k2 = 0; k2 < Q; ++k2) a[k1 + P * k2] = c[k2];
+    });
+  }
+  template <int RR, int QQ, int K1>
+  static constexpr int scaled_mask() {
+    int m = 0;
+    for (int n2 = 0; n2 < QQ; ++n2) {
+      const int k = ((n2 * K1) % RR + RR) % RR;
+      if (k != 0 && (8 * k) % RR == 0 && (((8 * k) / RR) & 1) == 1) m |= 1 << n2;
     }
+    return m;
   }
 };
 
@@ -183,6 +315,8 @@ __host__ __device__ constexpr int tw_offset(int N) {
 }
 constexpr int kTwiddleTotal = 2720;
 constexpr int kSupportedSizes[] = {64, 128, 192, 224, 256, 320, 512, 1024};
+// X-macro over the same lengths (one kernel instance per length in the launchers)
+#define PICS_FFT_SIZES(X) X(64) X(128) X(192) X(224) X(256) X(320) X(512) X(1024)
 
 // LDS layouts: Lay::addr(idx, seq) gives the slot of element idx of sequence
 // seq.  Column tiles keep T sequences side by side (row-major like global
@@ -208,9 +342,11 @@ struct RowLay {
 // DUAL: exchanges alternate between lds and lds_next and the barrier after
 // each exchange's reads is left out (the next exchange writes the other
 // buffer; the one after that is ordered by the next exchange's barrier).
-template <int N, int NT, int DIR, int Ns, class Lay, bool DUAL, int R, int... Rest>
+// SCALE_IN: the first stage transforms s[e] v[e] (the inputs scaled by the
+// real factors `in_scale`, e.g. a sampling mask); later stages ignore it.
+template <int N, int NT, int DIR, int Ns, class Lay, bool DUAL, bool SCALE_IN, int R, int... Rest>
 __device__ __forceinline__ void fft_stages(float2 (&v)[N / NT], int t, float2* lds, float2* lds_next, int seq,
-                                           const float2* __restrict__ tw) {
+                                           const float2* __restrict__ tw, const float (&in_scale)[N / NT]) {
   constexpr int E = N / NT;
   constexpr int Q = E / R;
   static_assert(E % R == 0, "radix must divide the elements per thread");
@@ -231,7 +367,17 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[N / NT], int t, float2* l
         u[r] = cmul(u[r], w);
       }
     }
-    Dft<R, DIR>::run(u);
+    if constexpr (SCALE_IN && Ns == 1) {
+      float us[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) us[r] = in_scale[q + r * Q];
+      if constexpr (R >= 8)
+        Dft<R, DIR>::run_in_scaled(u, us);
+      else
+        DftInScaled<R, DIR>::run(u, us);
+    } else {
+      Dft<R, DIR>::run(u);
+    }
     if constexpr (LAST) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q + r * Q] = u[r];
@@ -246,10 +392,10 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[N / NT], int t, float2* l
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = lds[Lay::addr(t + NT * e, seq)];
     if constexpr (DUAL) {
-      fft_stages<N, NT, DIR, Ns * R, Lay, DUAL, Rest...>(v, t, lds_next, lds, seq, tw);
+      fft_stages<N, NT, DIR, Ns * R, Lay, DUAL, SCALE_IN, Rest...>(v, t, lds_next, lds, seq, tw, in_scale);
     } else {
       __syncthreads();
-      fft_stages<N, NT, DIR, Ns * R, Lay, DUAL, Rest...>(v, t, lds, lds, seq, tw);
+      fft_stages<N, NT, DIR, Ns * R, Lay, DUAL, SCALE_IN, Rest...>(v, t, lds, lds, seq, tw, in_scale);
     }
   }
 }
@@ -262,10 +408,17 @@ struct RadixCount<Radices<Rs...>> { static constexpr int value = sizeof...(Rs); 
 template <int N>
 constexpr int kExchanges = RadixCount<typename Plan<N>::R>::value - 1;
 
-template <int N, int DIR, class Lay, bool DUAL, int... Rs>
+template <int N, int DIR, class Lay, bool DUAL, bool SCALE_IN = false, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[N / Plan<N>::NT], int t, float2* lds,
+                                        float2* lds_next, int seq, const float2* __restrict__ tw,
+                                        const float (&in_scale)[N / Plan<N>::NT]) {
+  fft_stages<N, Plan<N>::NT, DIR, 1, Lay, DUAL, SCALE_IN, Rs...>(v, t, lds, lds_next, seq, tw, in_scale);
+}
+template <int N, int DIR, class Lay, bool DUAL, int... Rs>
+__device__ __forceinline__ void fft_run(Radices<Rs...> r, float2 (&v)[N / Plan<N>::NT], int t, float2* lds,
                                         float2* lds_next, int seq, const float2* __restrict__ tw) {
-  fft_stages<N, Plan<N>::NT, DIR, 1, Lay, DUAL, Rs...>(v, t, lds, lds_next, seq, tw);
+  const float none[N / Plan<N>::NT] = {};
+  fft_run<N, DIR, Lay, DUAL, false>(r, v, t, lds, lds_next, seq, tw, none);
 }
 
 // In-place transform of the cyclic registers.  Every thread of the block must
@@ -286,6 +439,16 @@ template <int N, int DIR, class Lay>
 __device__ __forceinline__ void fft_dual(float2 (&v)[N / Plan<N>::NT], int t, float2* lds_a, float2* lds_b,
                                          int seq, const float2* __restrict__ tw) {
   fft_run<N, DIR, Lay, true>(typename Plan<N>::R{}, v, t, lds_a, lds_b, seq, tw);
+}
+
+// The transform of in_scale[e] v[e]: the real per-element factors (a sampling
+// mask with its normalisation) are folded into the first stage's additions.
+// Single-buffer (DUAL = false) or dual-buffer exchanges as fft / fft_dual.
+template <int N, int DIR, class Lay, bool DUAL>
+__device__ __forceinline__ void fft_in_scaled(float2 (&v)[N / Plan<N>::NT], const float (&in_scale)[N / Plan<N>::NT],
+                                              int t, float2* lds_a, float2* lds_b, int seq,
+                                              const float2* __restrict__ tw) {
+  fft_run<N, DIR, Lay, DUAL, true>(typename Plan<N>::R{}, v, t, lds_a, DUAL ? lds_b : lds_a, seq, tw, in_scale);
 }
 
 }  // namespace pics

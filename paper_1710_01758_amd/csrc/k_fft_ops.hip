@@ -160,8 +160,21 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
 #pragma unroll
     for (int e = 0; e < E; ++e) mbits |= (mk[t + NT * e] ? 1u : 0u) << e;
     const float inv_m = 1.0f / M;
-    const float2* __restrict__ S = w.sens + sd.coil + t * n + col;
+    float msc[E];  // mask / m per frequency row t + NT e
+#pragma unroll
+    for (int e = 0; e < E; ++e) msc[e] = ((mbits >> e) & 1u) ? inv_m : 0.f;
     const int plane = M * n;
+    // coil c's maps for this thread's rows, by buffer loads: the resource
+    // (the coil's plane) and the per-element offsets are wave-uniform, so the
+    // addresses cost no vector instructions
+    const int voff = (t * n + col) * (int)sizeof(float2);
+    auto load_maps = [&](float2(&dst)[E], int c) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(w.sens + sd.coil + (long long)c * plane), (short)0, plane * (int)sizeof(float2), 0x00020000);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        dst[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, NT * e * n * 8, 0));
+    };
     // the next coil's maps are prefetched, except at length 1024, where the
     // extra registers would spill, and at 320, where the registers they free
     // (with the halo loaded late) give two waves per SIMD instead of one
@@ -176,23 +189,17 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
       float2 v[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = cmul(cur[e], pv[e]);
-      if constexpr (PF) {
-        const float2* __restrict__ Sn = S + (long long)pf * plane;
-#pragma unroll
-        for (int e = 0; e < E; ++e) nxt[e] = Sn[NT * e * n];
-      }
+      if constexpr (PF) load_maps(nxt, pf);
+      // the mask (with the 1/m of the unitary pair) scales the inverse
+      // transform's inputs inside its first stage
       if constexpr (DUAL) {
         // exchanges alternate between the two buffers across both transforms
         constexpr bool odd = (kExchanges<M> & 1) != 0;
         fft_dual<M, -1, ColLay<T>>(v, t, lds, lds + LB, j, s_tw);
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ((mbits >> e) & 1u) ? inv_m : 0.f);
-        fft_dual<M, +1, ColLay<T>>(v, t, odd ? lds + LB : lds, odd ? lds : lds + LB, j, s_tw);
+        fft_in_scaled<M, +1, ColLay<T>, true>(v, msc, t, odd ? lds + LB : lds, odd ? lds : lds + LB, j, s_tw);
       } else {
         fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], ((mbits >> e) & 1u) ? inv_m : 0.f);
-        fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
+        fft_in_scaled<M, +1, ColLay<T>, false>(v, msc, t, lds, lds, j, s_tw);
       }
 #pragma unroll
       for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(cur[e], v[e]));
@@ -200,8 +207,7 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
     const std::integral_constant<bool, true> with_prefetch;
     const std::integral_constant<bool, false> without;
     float2 sa[E], sb[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) sa[e] = S[(long long)c0 * plane + NT * e * n];
+    load_maps(sa, c0);
     // lengths up to 256 with 16 or fewer elements per thread: two coils per
     // trip; the longer register files of 224 keep one coil per trip (four
     // inlined transforms would spill)
@@ -224,19 +230,10 @@ __global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void
       }
     } else {
       for (int c = c0; c < sd.nc; c += cstep) {
-        if (!PREFETCH && c != c0) {
-          const float2* __restrict__ Sc = S + (long long)c * plane;
-#pragma unroll
-          for (int e = 0; e < E; ++e) sa[e] = Sc[NT * e * n];
-        }
-        if (PREFETCH) {
-          // unconditional (the last trip reloads its own maps): a
-          // conditional load makes the compiler wait on it before the
-          // transforms
-          const float2* __restrict__ Sn = S + (long long)(c + cstep < sd.nc ? c + cstep : c) * plane;
-#pragma unroll
-          for (int e = 0; e < E; ++e) sb[e] = Sn[NT * e * n];
-        }
+        if (!PREFETCH && c != c0) load_maps(sa, c);
+        // unconditional (the last trip reloads its own maps): a conditional
+        // load makes the compiler wait on it before the transforms
+        if (PREFETCH) load_maps(sb, c + cstep < sd.nc ? c + cstep : c);
         coil_step(without, sa, sb, 0);
         if (PREFETCH) {
 #pragma unroll
@@ -759,8 +756,6 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, co
 }
 
 // ============================================================== launchers
-
-#define PICS_FFT_SIZES(X) X(64) X(128) X(192) X(224) X(256) X(320) X(512) X(1024)
 
 template <int M, int PH>
 void launch_col_apply_phase(dim3 grid, const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
