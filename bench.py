@@ -86,6 +86,28 @@ def run_apply_mode(torch, ctx, insts):
                       "achieved_GBs": round(b / t_apply / 1e9, 1), "copy_cal_bytes": COPY_CAL_BYTES}), flush=True)
 
 
+def run_apply_ragged(torch, B):
+    """The ragged 64-slice batch's operator: the whole batch (size groups on
+    side streams), then each size group alone in its own context (one JSON
+    line each)."""
+    specs = gen.cfg4_specs()
+    insts = [gen.make_instance(sp, gen.eval_seed(4, i)) for i, sp in enumerate(specs)]
+    groups = [("all", insts)]
+    for shape in gen.CFG4_SHAPES:
+        groups.append((f"{shape[0]}x{shape[1]}", [it for it in insts if (it.spec.m, it.spec.n) == shape]))
+    for label, gi in groups:
+        ctx, _ = B.context_for(gi)
+        split = ctx.autotune()
+        xa = torch.randn(ctx.image_elems, dtype=torch.complex64, device="cuda")
+        ya = torch.empty_like(xa)
+        t = time_apply_kernel(torch, ctx, xa, ya, reps=20)
+        b = apply_bytes([i.spec for i in gi])
+        print(json.dumps({"group": label, "slices": len(gi), "coils": sum(i.spec.ncoils for i in gi),
+                          "coil_split": split, "apply_avg_us": round(t * 1e6, 2), "bytes_per_launch": b,
+                          "achieved_GBs": round(b / t / 1e9, 1)}), flush=True)
+        ctx.close()
+
+
 def run_pcg_mode(torch, ctx, iters=10, reps=5):
     """Iteration-locked PCG solves (every slice runs exactly `iters`
     iterations from x = 0, circulant preconditioner), so that every launch
@@ -379,13 +401,23 @@ def volume_section(torch, B):
         out[kind] = {"pcg_iters": it, "relres": rel, "solve_s": round(time.perf_counter() - t0, 4),
                      "build_s": round(tb, 4)}
     y = torch.empty_like(b)
-    vol.apply_A(b, y)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(5):
+    for _ in range(2):
         vol.apply_A(b, y)
-    torch.cuda.synchronize()
-    out["apply_A_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+    st = torch.cuda.ExternalStream(vol.stream) if vol.stream else torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(st)
+    for _ in range(reps):
+        vol.apply_A(b, y)
+    e1.record(st)
+    e1.synchronize()
+    t_apply = e0.elapsed_time(e1) / reps * 1e-3
+    floor = 8 * spec.p * spec.m * spec.n * (spec.ncoils + 2)
+    out["apply_A_ms"] = round(t_apply * 1e3, 3)
+    out["apply_roofline"] = {"bound": "hbm", "achieved": round(floor / t_apply / 1e9, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(floor / t_apply / 1e9 / HBM_PEAK_GBS, 4),
+                             "bytes_per_launch": floor,
+                             "note": "algorithmic floor 8 V (N_c + 2): read x and the coil maps, write y"}
     vol.close()
     return out
 
@@ -525,9 +557,11 @@ def main():
                     help="skip the 512^2 x 32 slice, the ragged batch, the 2D-mask batch and the "
                          "parameter-set comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
-    ap.add_argument("--mode", choices=["full", "apply", "apply2d", "pcg"], default="full",
+    ap.add_argument("--mode", choices=["full", "apply", "apply2d", "apply_ragged", "pcg", "volume"], default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs); "
                          "apply2d: the same for the 2D-mask operator (256^2 x 12, batch of 32); "
+                         "apply_ragged: the ragged 64-slice batch's operator, whole and per size group; "
+                         "volume: the 3D section alone; "
                          "pcg: iteration-locked PCG solves over 128 slices (for kernel traces)")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-procs", type=int, default=16,
@@ -558,6 +592,12 @@ def main():
         insts2 = [gen.make_instance(spec2, gen.eval_seed(6, i)) for i in range(32)]
         ctx2, _ = B.context_for(insts2)
         run_apply_mode(torch, ctx2, insts2)
+        return
+    if a.mode == "apply_ragged":
+        run_apply_ragged(torch, B)
+        return
+    if a.mode == "volume":
+        print(json.dumps(volume_section(torch, B)), flush=True)
         return
     spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=a.scale)
     if a.mode in ("apply", "pcg"):

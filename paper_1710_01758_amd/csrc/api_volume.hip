@@ -32,6 +32,7 @@ struct pics3d_ctx {
   SliceDev *planes_coil, *planes_vol, *z_coil, *z_vol;
   int* idx;  // 0, 1, 2, ... (grid.y -> slice)
   bool built = false;
+  bool xconst = false;  // mask constant along x: the operator's three-pass (z, y) path
   char err[256] = {0};
 };
 
@@ -84,6 +85,15 @@ int fft3(pics3d_ctx* c, float2* buf, int count, int inverse, float2* scratch) {
 
 int apply3(pics3d_ctx* c, const float2* x, float2* y) {
   const int nc = c->d.ncoils;
+  if (c->xconst) {
+    // F^H R F = (F_zy^H R_zy F_zy) (x) I_x: transforms along y and z only
+    const int p = c->d.p, m = c->d.m, n = c->d.n;
+    HIPCHK3(c, launch3_col_sp(c->stream, c->sens, x, c->coil, c->tw, nc, p, m, n));
+    HIPCHK3(c, launch3_col_z(c->stream, c->coil, c->mask, c->tw, nc, p, m, n, (float)(1.0 / ((double)p * m))));
+    HIPCHK3(c, launch3_col_acc(c->stream, c->sens, c->coil, x, y, c->tw, nc, p, m, n, (float)c->d.mu,
+                               (float)c->d.lambda, (float)c->d.gamma, 1));
+    return PICS_OK;
+  }
   HIPCHK3(c, launch3_coil_mul(c->stream, c->sens, x, c->coil, nc, c->V));
   // the coil transforms use the second half of the coil workspace as scratch
   float2* scratch = c->coil + (long long)nc * c->V;
@@ -179,6 +189,12 @@ int pics3d_create(pics3d_ctx** out, const pics3d_desc* d, const void* sens, cons
             hipMemcpy(c->idx, idx.data(), sizeof(int) * nplanes, hipMemcpyHostToDevice) == hipSuccess &&
             hipHostMalloc((void**)&c->flag_host, sizeof(int)) == hipSuccess &&
             hipHostMalloc((void**)&c->scal_host, sizeof(double) * 8) == hipSuccess;
+  // is the mask constant along x?  (then the operator skips the x transforms)
+  ok = ok && hipMemsetAsync(c->bad, 0, sizeof(int), c->stream) == hipSuccess &&
+       launch3_xconst(c->stream, mask, (long long)p * m, n, c->bad) == hipSuccess &&
+       hipMemcpyAsync(c->flag_host, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream) == hipSuccess &&
+       hipStreamSynchronize(c->stream) == hipSuccess;
+  if (ok) c->xconst = *c->flag_host == 0;
   if (!ok) {
     if (c->flag_host) (void)hipHostFree(c->flag_host);
     if (c->scal_host) (void)hipHostFree(c->scal_host);

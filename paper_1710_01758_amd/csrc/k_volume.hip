@@ -2,7 +2,7 @@
 // axis 0 = z).  The 3D transforms themselves reuse the row and column FFT
 // kernels through slice tables that view a volume as p planes of m x n (row
 // and column passes) and as one [p][m n] array (the z pass).
-#include "internal.hpp"
+#include "tiles.hpp"
 
 namespace pics {
 
@@ -101,6 +101,167 @@ __global__ __launch_bounds__(256) void k3_build_k(const float2* __restrict__ a, 
 __global__ __launch_bounds__(256) void k3_scale(float2* __restrict__ buf, const float* __restrict__ s, long long V) {
   for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V; v += (long long)gridDim.x * blockDim.x)
     buf[v] = cscale(buf[v], s[v]);
+}
+
+// ----------------------------------------------------------------------------
+// Operator for masks that are constant along x (axis 2; the generators' 2D
+// variable-density pattern over (z, y) with x fully sampled).  Then the 3D
+// data term factors as F^H R F = (F_zy^H R_zy F_zy) (x) I_x: each coil needs
+// transforms along y and z only, and x is the contiguous batch axis of every
+// pass.  Three passes over the coil workspace [nc][p][m][n]:
+//   1. y-columns of each plane:  u_c = F_y (S_c x)                     (k3_col_sp)
+//   2. z-columns of each coil:   u_c = F_z^H (r / (p m)) F_z u_c        (k3_col_z)
+//   3. y-columns of each plane:  y = mu sum_c conj(S_c) F_y^H u_c
+//                                    + lam (D_z^H D_z + D_y^H D_y + D_x^H D_x) x + gam x  (k3_col_acc)
+// Each column workgroup owns T adjacent x columns of one plane (passes 1, 3)
+// or of the flattened (y, x) index (pass 2) and the whole transform length.
+// ----------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(ColCfg<M>::THREADS) void k3_col_sp(const float2* __restrict__ S,
+                                                                const float2* __restrict__ x,
+                                                                float2* __restrict__ coil,
+                                                                const float2* __restrict__ tw, int nc, int n,
+                                                                long long V) {
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T, TH = ColCfg<M>::THREADS;
+  __shared__ float2 lds[ColLay<T>::template size<M>];
+  __shared__ float2 s_tw[M];
+  const int j = threadIdx.x % T, t = threadIdx.x / T;
+  const long long base =
+      (long long)blockIdx.y * M * n + (long long)xcd_tile(blockIdx.x, gridDim.x) * T + j + (long long)t * n;
+  stage_twiddles<M, TH>(s_tw, tw);
+  float2 xv[E], sv[E], sn[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    xv[e] = x[base + (long long)NT * e * n];
+    sv[e] = S[base + (long long)NT * e * n];
+  }
+  for (int c = 0; c < nc; ++c) {
+    const long long off = (long long)c * V + base;
+    // the next coil's maps are loaded while this coil is transformed
+    // (unconditional: the last trip reloads its own)
+    const long long nx = c + 1 < nc ? V : 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) sn[e] = S[off + nx + (long long)NT * e * n];
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cmul(sv[e], xv[e]);
+    fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) coil[off + (long long)NT * e * n] = v[e];
+#pragma unroll
+    for (int e = 0; e < E; ++e) sv[e] = sn[e];
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(ColCfg<P>::THREADS) void k3_col_z(float2* __restrict__ coil,
+                                                               const uint8_t* __restrict__ mask,
+                                                               const float2* __restrict__ tw, long long mn,
+                                                               long long V, float scale) {
+  constexpr int NT = ColCfg<P>::NT, E = ColCfg<P>::E, T = ColCfg<P>::T, TH = ColCfg<P>::THREADS;
+  __shared__ float2 lds[ColLay<T>::template size<P>];
+  __shared__ float2 s_tw[P];
+  const int j = threadIdx.x % T, t = threadIdx.x / T;
+  const long long col = (long long)xcd_tile(blockIdx.x, gridDim.x) * T + j;  // (y, x) index in a plane
+  float2* __restrict__ cb = coil + (long long)blockIdx.y * V + col;
+  stage_twiddles<P, TH>(s_tw, tw);
+  float2 v[E];
+  float sc[E];  // r(z, y) / (p m): the pair's scale folded into the mask
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    v[e] = cb[(long long)(t + NT * e) * mn];
+    sc[e] = mask[(long long)(t + NT * e) * mn + col] ? scale : 0.f;
+  }
+  fft<P, -1, ColLay<T>>(v, t, lds, j, s_tw);
+  fft_in_scaled<P, +1, ColLay<T>, false>(v, sc, t, lds, lds, j, s_tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) cb[(long long)(t + NT * e) * mn] = v[e];
+}
+
+template <int M>
+struct Acc3Cfg {
+  static constexpr int T = ColCfg<M>::T;
+  static constexpr int TS = T + 2;  // tile stride with the two halo x columns
+  static constexpr int LB = ColLay<T>::template size<M>;
+  static constexpr int LDS = LB > M * TS ? LB : M * TS;
+};
+
+template <int M>
+__global__ __launch_bounds__(ColCfg<M>::THREADS) void k3_col_acc(const float2* __restrict__ S,
+                                                                 const float2* __restrict__ coil,
+                                                                 const float2* __restrict__ x, float2* __restrict__ y,
+                                                                 const float2* __restrict__ tw, int nc, int p, int n,
+                                                                 long long V, float mu, float lam, float gam,
+                                                                 int data) {
+  constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T, TH = ColCfg<M>::THREADS;
+  constexpr int TS = Acc3Cfg<M>::TS;
+  __shared__ float2 lds[Acc3Cfg<M>::LDS];
+  __shared__ float2 s_tw[M];
+  const int j = threadIdx.x % T, t = threadIdx.x / T;
+  const int w = blockIdx.y;
+  const int j0 = xcd_tile(blockIdx.x, gridDim.x) * T;
+  const long long pl = (long long)M * n;
+  const long long base = (long long)w * pl + j0 + j + (long long)t * n;
+  stage_twiddles<M, TH>(s_tw, tw);
+  float2 acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
+  if (data) {
+    // the next coil's column and maps are loaded while this coil is transformed
+    float2 v[E], vn[E], sv[E], sn[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v[e] = coil[base + (long long)NT * e * n];
+      sv[e] = S[base + (long long)NT * e * n];
+    }
+    for (int c = 0; c < nc; ++c) {
+      const long long nx = (long long)(c + 1 < nc ? c + 1 : c) * V + base;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        vn[e] = coil[nx + (long long)NT * e * n];
+        sn[e] = S[nx + (long long)NT * e * n];
+      }
+      fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cconjmul(sv[e], v[e]));
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        v[e] = vn[e];
+        sv[e] = sn[e];
+      }
+    }
+    __syncthreads();  // the transforms are done with the LDS buffer
+  }
+  // x on the plane's tile with one halo column on each side (periodic in x)
+  for (int k = threadIdx.x; k < M * TS; k += TH) {
+    const int u = k / TS, jj = k % TS;
+    const int gj = (j0 - 1 + jj + n) % n;
+    lds[k] = x[(long long)w * pl + (long long)u * n + gj];
+  }
+  __syncthreads();
+  const long long wu = (long long)((w + 1) % p) * pl, wd = (long long)((w - 1 + p) % p) * pl;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int u = t + NT * e;
+    const float2 c0 = lds[u * TS + j + 1];
+    const float2 up = lds[((u + 1) % M) * TS + j + 1], dn = lds[((u - 1 + M) % M) * TS + j + 1];
+    const float2 l = lds[u * TS + j], r = lds[u * TS + j + 2];
+    const long long o = (long long)u * n + j0 + j;
+    const float2 zu = x[wu + o], zd = x[wd + o];
+    const float2 lap = make_float2(6.f * c0.x - up.x - dn.x - l.x - r.x - zu.x - zd.x,
+                                   6.f * c0.y - up.y - dn.y - l.y - r.y - zu.y - zd.y);
+    y[(long long)w * pl + o] = make_float2(mu * acc[e].x + lam * lap.x + gam * c0.x,
+                                           mu * acc[e].y + lam * lap.y + gam * c0.y);
+  }
+}
+
+// flag |= 1 if the mask [rows][n] is not constant along its last axis
+__global__ __launch_bounds__(256) void k3_xconst(const uint8_t* __restrict__ mask, long long rows, int n,
+                                                 int* __restrict__ flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < rows * n; i += (long long)gridDim.x * blockDim.x)
+    if ((mask[i] != 0) != (mask[(i / n) * n] != 0)) bad = 1;
+  if (bad) atomicOr(flag, 1);
 }
 
 // ---------------------------------------------------------------- PCG
@@ -211,6 +372,64 @@ hipError_t launch3_update_xr(hipStream_t st, float2* x, float2* r, const float2*
 hipError_t launch3_update_p(hipStream_t st, float2* p, const float2* z, const double* scal, int inew, int iold,
                             long long V) {
   hipLaunchKernelGGL(k3_update_p, vol_grid(V), dim3(256), 0, st, p, z, scal, inew, iold, V);
+  return hipGetLastError();
+}
+
+
+hipError_t launch3_col_sp(hipStream_t st, const float2* S, const float2* x, float2* coil, const float2* tw, int nc,
+                          int p, int m, int n) {
+  const long long V = (long long)p * m * n;
+  const dim3 grid(n / col_tile(m), p);
+  switch (m) {
+#define PICS_CASE(M)                                                                                            \
+  case M:                                                                                                       \
+    hipLaunchKernelGGL(k3_col_sp<M>, grid, dim3(ColCfg<M>::THREADS), 0, st, S, x, coil, tw, nc, n, V);          \
+    break;
+    PICS_FFT_SIZES(PICS_CASE)
+#undef PICS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch3_col_z(hipStream_t st, float2* coil, const uint8_t* mask, const float2* tw, int nc, int p, int m,
+                         int n, float scale) {
+  const long long mn = (long long)m * n, V = (long long)p * mn;
+  const dim3 grid((unsigned)(mn / col_tile(p)), nc);
+  switch (p) {
+#define PICS_CASE(P)                                                                                      \
+  case P:                                                                                                 \
+    hipLaunchKernelGGL(k3_col_z<P>, grid, dim3(ColCfg<P>::THREADS), 0, st, coil, mask, tw, mn, V, scale); \
+    break;
+    PICS_FFT_SIZES(PICS_CASE)
+#undef PICS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch3_col_acc(hipStream_t st, const float2* S, const float2* coil, const float2* x, float2* y,
+                           const float2* tw, int nc, int p, int m, int n, float mu, float lam, float gam, int data) {
+  const long long V = (long long)p * m * n;
+  const dim3 grid(n / col_tile(m), p);
+  switch (m) {
+#define PICS_CASE(M)                                                                                          \
+  case M:                                                                                                     \
+    hipLaunchKernelGGL(k3_col_acc<M>, grid, dim3(ColCfg<M>::THREADS), 0, st, S, coil, x, y, tw, nc, p, n, V, \
+                       mu, lam, gam, data);                                                                   \
+    break;
+    PICS_FFT_SIZES(PICS_CASE)
+#undef PICS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch3_xconst(hipStream_t st, const uint8_t* mask, long long rows, int n, int* flag) {
+  hipLaunchKernelGGL(k3_xconst, vol_grid(rows * n), dim3(256), 0, st, mask, rows, n, flag);
   return hipGetLastError();
 }
 
