@@ -229,7 +229,15 @@ int pics_coil_compress(pics_ctx* ctx, const void* kspace, int32_t nvirt, void* k
  *   (to 2, then doubling).  0 disables the graph.  Default 1.
  * PICS_OPT_COIL_GROUPS: split every column tile's coil loop over this many
  *   workgroups (clamped to each group's coil count), overriding the
- *   autotuner; 1 = no split (the default before pics_autotune).
+ *   autotuner; 1 = no split (the default before pics_autotune).  A split
+ *   above 1 runs with the default column tiles.
+ * PICS_OPT_COL_TILE: columns per workgroup of the line-mask operator for
+ *   every size group, overriding the autotuner: 0 = the default (16 up to
+ *   length 320, 4 at 512, 8 at 1024) or one of the two alternatives of each
+ *   length (8 and 32 at 64, 128 and 224; 8 and 4 at 192, 256 and 320; 8 and
+ *   2 at 512; 4 and 2 at 1024), at most 256 tiles per slice;
+ *   PICS_ERR_INVALID otherwise.  A width other than the default resets the
+ *   coil split to 1.
  * PICS_OPT_CONCURRENT_GROUPS: 1 (default) runs the per-size-group kernels of
  *   a batch with several slice sizes on side streams of the context (forked
  *   from and joined back to the caller's stream with events, also under
@@ -239,6 +247,7 @@ int pics_coil_compress(pics_ctx* ctx, const void* kspace, int32_t nvirt, void* k
 #define PICS_OPT_GRAPH_BUDGET 2
 #define PICS_OPT_COIL_GROUPS 3
 #define PICS_OPT_CONCURRENT_GROUPS 4
+#define PICS_OPT_COL_TILE 5
 int pics_set_option(pics_ctx* ctx, int32_t key, int64_t value);
 
 /* ---------------------------------------------------------------------------
@@ -301,12 +310,14 @@ int pics_net_adam_step(pics_net* net, float lr);
 int pics_net_correction(pics_net* net, pics_ctx* ctx, const float* features, float* correction);
 
 /* Autotuner.  Per group of equal-size slices, times the fused operator for
- * each way of splitting a column tile's coil loop over 1, 2, 3, 4, 6, 8 or 12
- * workgroups (the split adds the groups' partial sums in a second pass, in
- * fixed order) and keeps the fastest for every later call.  Choices are
- * cached per (GPU arch, CU count, m, n, largest coil count, slices) in
- * $PICS_TUNE_CACHE (default ~/.cache/pics_autotune.txt).  Synchronises the
- * stream; allocates the partial-sum workspace when a split is chosen.
+ * each launch shape -- the default column tiles with each way of splitting a
+ * tile's coil loop over 1, 2, 3, 4, 6, 8 or 12 workgroups (the split adds the
+ * groups' partial sums in a second pass, in fixed order), and the two
+ * alternative tile widths of the length (PICS_OPT_COL_TILE) without a split
+ * -- and keeps the fastest for every later call.  Choices are cached per (GPU
+ * arch, CU count, m, n, largest coil count, slices) in $PICS_TUNE_CACHE
+ * (default ~/.cache/pics_autotune.txt).  Synchronises the stream; allocates
+ * the partial-sum workspace when a split is chosen.
  * flags: PICS_TUNE_FORCE re-times even if cached; PICS_TUNE_NO_WRITE keeps
  * the cache file unchanged. */
 #define PICS_TUNE_FORCE 1
@@ -315,6 +326,9 @@ int pics_autotune(pics_ctx* ctx, int32_t flags);
 /* Chosen coil split per size group (in order of first appearance); returns
  * the number of groups. */
 int pics_get_tuning(const pics_ctx* ctx, int32_t* coil_groups, int32_t max_groups);
+/* Chosen column-tile width per size group (0 for groups with 2D masks);
+ * returns the number of groups. */
+int pics_get_tuning_tiles(const pics_ctx* ctx, int32_t* tiles, int32_t max_groups);
 
 const char* pics_status_string(int status);
 const char* pics_last_error(const pics_ctx* ctx);

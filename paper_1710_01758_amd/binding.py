@@ -29,6 +29,7 @@ OPT_POLL_CHUNK = 1
 OPT_GRAPH_BUDGET = 2
 OPT_COIL_GROUPS = 3
 OPT_CONCURRENT_GROUPS = 4
+OPT_COL_TILE = 5
 TUNE_FORCE = 1
 TUNE_NO_WRITE = 2
 
@@ -74,6 +75,7 @@ def signatures():
         "pics_autotune": (ctypes.c_int, [vp, i32]),
         "pics_coil_compress": (ctypes.c_int, [vp, vp, i32, vp, vp, pdbl]),
         "pics_get_tuning": (ctypes.c_int, [vp, pi32, i32]),
+        "pics_get_tuning_tiles": (ctypes.c_int, [vp, pi32, i32]),
         "pics_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pics_last_error": (ctypes.c_char_p, [vp]),
         "pics_features": (ctypes.c_int, [vp, vp, vp]),
@@ -195,6 +197,12 @@ class Context:
     def tuning(self):
         buf = (ctypes.c_int32 * 64)()
         ng = self._check(self.L.pics_get_tuning(self.h, buf, 64))
+        return [int(buf[i]) for i in range(ng)]
+
+    def tuning_tiles(self):
+        """Column-tile width of the line-mask operator per size group."""
+        buf = (ctypes.c_int32 * 64)()
+        ng = self._check(self.L.pics_get_tuning_tiles(self.h, buf, 64))
         return [int(buf[i]) for i in range(ng)]
 
     # -- entry points (same names as the C ABI)

@@ -37,6 +37,7 @@ struct pics_ctx {
     std::vector<int> idx;
     int* idx_dev;
     int coil_groups = 1;  // workgroups sharing one tile's coil loop (autotuned)
+    int tile = 0;         // column-tile width of the line-mask operator (autotuned; 0 = col_tile(m))
     int nc_max = 0;
     int sidx = 0;         // index of the group's side stream
     int mask_kind = 0;    // PICS_MASK_LINES or PICS_MASK_2D (slices of one group share it)
@@ -240,8 +241,10 @@ hipError_t launch_operator(pics_ctx* c, const pics_ctx::Group& g, int mode, int 
     split = g.coil_groups;
     dpart = c->dpart;
   }
+  // a coil split runs with the default tiles (the tuner never pairs the two)
+  const int tile = split > 1 ? 0 : g.tile;
   return launch_col_apply(make_launch(c, g), ws_for(c, g), mode, terms, pk, tol, xin, zsrc, pold, pn, out, split,
-                          dpart, c->img_total);
+                          dpart, c->img_total, tile);
 }
 
 }  // namespace
@@ -343,7 +346,25 @@ const char* pics_status_string(int s) {
 
 const char* pics_last_error(const pics_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-namespace { int ensure_dpart(pics_ctx* c, int groups); }
+namespace {
+int ensure_dpart(pics_ctx* c, int groups);
+
+// Column-tile width of a group's line-mask operator; the slices' sigma
+// partial count (one per tile) follows it on the host and device tables.
+int set_group_tile(pics_ctx* c, pics_ctx::Group& g, int tile) {
+  if (tile == col_tile(g.m)) tile = 0;
+  if (tile == g.tile) return PICS_OK;
+  g.tile = tile;
+  const int ct = g.n / (tile ? tile : col_tile(g.m));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int s : g.idx) {
+    c->sl[s].ctiles = ct;
+    HIPCHK(c, hipMemcpy(c->sl_dev + s, &c->sl[s], sizeof(SliceDev), hipMemcpyHostToDevice));
+  }
+  ++c->tuning_gen;
+  return PICS_OK;
+}
+}  // namespace
 
 int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
   if (!c) return PICS_ERR_INVALID;
@@ -367,9 +388,29 @@ int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
     if (value < 1 || value > 64) return fail(c, PICS_ERR_INVALID, "coil split out of range");
     int need = 1;
     for (auto& g : c->groups) need = std::max(need, std::min((int)value, g.nc_max));
-    const int rc = ensure_dpart(c, need);
+    int rc = ensure_dpart(c, need);
     if (rc) return rc;
-    for (auto& g : c->groups) g.coil_groups = std::min((int)value, g.nc_max);
+    for (auto& g : c->groups) {
+      g.coil_groups = std::min((int)value, g.nc_max);
+      if (g.coil_groups > 1 && (rc = set_group_tile(c, g, 0))) return rc;
+    }
+    ++c->tuning_gen;
+    return PICS_OK;
+  }
+  if (key == PICS_OPT_COL_TILE) {
+    for (auto& g : c->groups) {
+      if (g.mask_kind != PICS_MASK_LINES) continue;
+      const int tile = value == 0 ? col_tile(g.m) : (int)value;
+      if (value < 0 || value > 64 || !apply_tile_ok(g.m, g.n, tile))
+        return fail(c, PICS_ERR_INVALID, "column tile %lld not available for %d x %d slices", (long long)value, g.m,
+                    g.n);
+    }
+    for (auto& g : c->groups) {
+      if (g.mask_kind != PICS_MASK_LINES) continue;
+      const int rc = set_group_tile(c, g, value == 0 ? 0 : (int)value);
+      if (rc) return rc;
+      if (value != 0) g.coil_groups = 1;
+    }
     ++c->tuning_gen;
     return PICS_OK;
   }
@@ -445,6 +486,7 @@ int pics_create(pics_ctx** out, int32_t nslices, const pics_desc* descs, const v
     sd.mu = (float)d.mu;
     sd.lam = (float)d.lambda;
     sd.gam = (float)d.gamma;
+    sd.ctiles = d.n / col_tile(d.m);
     sd.img = c->img_total;
     sd.coil = c->coil_total;
     sd.mask = c->mask_total;
@@ -1367,11 +1409,13 @@ int pics_net_correction(pics_net* n, pics_ctx* c, const float* features, float* 
 }  // extern "C"
 
 // ================================================================= autotuner
-// Per group of equal-size slices, time the fused operator for each coil split
-// (1, 2, 3, 4, 6, 8, 12 workgroups per column tile) with HIP events and keep
-// the fastest.  Results are cached per (GPU arch, CU count, m, n, largest coil
-// count, slices in the group) in a text file ($PICS_TUNE_CACHE, default
-// ~/.cache/pics_autotune.txt).
+// Per group of equal-size slices, time the fused operator for each launch
+// shape: the default column tiles with each coil split (1, 2, 3, 4, 6, 8, 12
+// workgroups per tile), and the two alternative tile widths of the length
+// without a split; keep the fastest (HIP events).  Results are cached per
+// (GPU arch, CU count, m, n, largest coil count, slices in the group) in a
+// text file ($PICS_TUNE_CACHE, default ~/.cache/pics_autotune.txt) as
+// tile x 100 + split.
 namespace {
 
 std::atomic<long> tune_tmp_counter{0};
@@ -1470,23 +1514,35 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
   for (auto& g : c->groups) {
     if (g.mask_kind == PICS_MASK_2D) continue;  // the 2D path has no coil split
     const std::string key = group_key(g);
+    const int tdef = col_tile(g.m);
     auto hit = cache.find(key);
-    if (hit != cache.end() && hit->second >= 1 && hit->second <= g.nc_max) {
-      int rc = ensure_dpart(c, hit->second);
-      if (rc) return rc;
-      g.coil_groups = hit->second;
-      continue;
+    if (hit != cache.end()) {
+      // cached value: tile x 100 + coil split (a bare split: the default tiles)
+      const int v = hit->second, tile = v >= 100 ? v / 100 : tdef, G = v >= 100 ? v % 100 : v;
+      if (G >= 1 && G <= g.nc_max && apply_tile_ok(g.m, g.n, tile) && (G == 1 || tile == tdef)) {
+        int rc = ensure_dpart(c, G);
+        if (!rc) rc = set_group_tile(c, g, tile);
+        if (rc) return rc;
+        g.coil_groups = G;
+        continue;
+      }
     }
-    const int cands[] = {1, 2, 3, 4, 6, 8, 12};
+    // candidates: the default tiles with each coil split, then the two
+    // alternative tile widths without a split
+    std::vector<std::pair<int, int>> cands;
+    for (int G : {1, 2, 3, 4, 6, 8, 12})
+      if (G <= g.nc_max) cands.push_back({tdef, G});
+    for (int k = 0; k < 2; ++k)
+      if (apply_tile_ok(g.m, g.n, apply_tile_alt(g.m, k))) cands.push_back({apply_tile_alt(g.m, k), 1});
     float best_ms = 1e30f;
-    int best = 1;
-    for (int G : cands) {
-      if (G > g.nc_max) break;
+    std::pair<int, int> best{tdef, 1};
+    for (auto cand : cands) {
+      const int tile = cand.first, G = cand.second;
       int rc = ensure_dpart(c, G);
       if (rc) return rc;
       auto run = [&]() {
         return launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, c->pk, 0.0, c->p, nullptr,
-                                nullptr, nullptr, c->q, G, c->dpart, c->img_total);
+                                nullptr, nullptr, c->q, G, c->dpart, c->img_total, tile);
       };
       for (int k = 0; k < 2; ++k) HIPCHK(c, run());
       HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -1497,13 +1553,15 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
       float ms = 0.f;
       HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
       ms /= reps;
-      if (ms < best_ms * 0.97f) {  // a split must win by 3% to be taken
+      if (ms < best_ms * 0.97f) {  // a later candidate must win by 3% to be taken
         best_ms = ms;
-        best = G;
+        best = cand;
       }
     }
-    g.coil_groups = best;
-    cache[key] = best;
+    int rc = set_group_tile(c, g, best.first);
+    if (rc) return rc;
+    g.coil_groups = best.second;
+    cache[key] = best.first * 100 + best.second;
     changed = true;
   }
   ++c->tuning_gen;
@@ -1514,6 +1572,15 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
 int pics_get_tuning(const pics_ctx* c, int32_t* coil_groups, int32_t max_groups) {
   if (!c || !coil_groups) return PICS_ERR_INVALID;
   for (int i = 0; i < (int)c->groups.size() && i < max_groups; ++i) coil_groups[i] = c->groups[i].coil_groups;
+  return (int)c->groups.size();
+}
+
+int pics_get_tuning_tiles(const pics_ctx* c, int32_t* tiles, int32_t max_groups) {
+  if (!c || !tiles) return PICS_ERR_INVALID;
+  for (int i = 0; i < (int)c->groups.size() && i < max_groups; ++i) {
+    const auto& g = c->groups[i];
+    tiles[i] = g.mask_kind == PICS_MASK_LINES ? (g.tile ? g.tile : col_tile(g.m)) : 0;
+  }
   return (int)c->groups.size();
 }
 

@@ -13,6 +13,16 @@ namespace pics {
 #endif
 constexpr int kColT = PICS_COLT;
 __host__ __device__ constexpr int col_tile(int m) { return m >= 1024 ? 8 : m >= 512 ? 4 : kColT; }
+// The fused operator's alternative tile widths (autotuner candidates besides
+// col_tile(m)), two per length, each giving workgroups of 64 to 1024 threads:
+// 8 and 32 at the lengths carried by 8 threads per column (64, 128, 224), 8
+// and 4 at those with 16 (192, 256, 320), 8 and 2 at 512, 4 and 2 at 1024.
+__host__ __device__ constexpr int apply_tile_alt(int m, int k) {
+  return m >= 1024 ? (k == 0 ? 4 : 2)
+       : m >= 512  ? (k == 0 ? 8 : 2)
+       : (m == 64 || m == 128 || m == 224) ? (k == 0 ? 8 : 32)
+                                            : (k == 0 ? 8 : 4);
+}
 constexpr int kRowRR = 16;    // rows per row tile
 constexpr int kPartMax = 256;  // partial sums per slice per reduction (n / col_tile(m) <= 256)
 
@@ -32,7 +42,7 @@ struct SliceDev {
   int m, n, nc, mask_kind;  // mask_kind: 0 = line mask uint8[m], 1 = 2D uint8[m][n]
   int wavelet, levels;      // 0 none, 1 haar, 2 db4
   float mu, lam, gam;
-  int pad0;
+  int ctiles;  // column tiles of the line-mask operator (n / its tile width): sigma partials per solve
   long long img;   // element offset of the slice in packed image-shaped buffers
   long long coil;  // element offset in packed coil-shaped buffers [nc][m][n]
   long long mask;  // byte offset in the packed mask buffer
@@ -159,9 +169,13 @@ bool fft_size_supported(int N);
 // ngroups > 1 splits the coil loop over that many workgroups per tile
 // (partial data terms in dpart[group][image-packed], stride dstride elements)
 // and adds them in a second pass.
+// tile: the operator's column-tile width (0 = col_tile(m); else one of
+// apply_tile_alt(m, 0 / 1), with no coil split).
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            int ngroups = 1, float2* dpart = nullptr, long long dstride = 0);
+                            int ngroups = 1, float2* dpart = nullptr, long long dstride = 0, int tile = 0);
+// tile widths launch_col_apply accepts for an m x n slice
+bool apply_tile_ok(int m, int n, int tile);
 // RU_SETUP also resets the slices' PCG state (iteration limit maxit, or
 // maxit_ps[slice] when given)
 hipError_t launch_row_update(const Launch& L, const Ws& w, int mode, int pk, const float2* b, const float2* q,

@@ -29,12 +29,13 @@ namespace pics {
 //    AP_FIN    adds the partial sums in group order, then the diagonal terms
 //              and the mode's outputs (CA_PCG reads p back from pn)
 // ----------------------------------------------------------------------------
-template <int M, int MODE, int PH>
-__global__ __launch_bounds__(ApplyCfg<M>::THREADS, ApplyCfg<M>::MIN_BLOCKS) void k_col_apply(
+template <int M, int MODE, int PH, int TW = col_tile(M)>
+__global__ __launch_bounds__((ApplyCfg<M, TW>::THREADS), (ApplyCfg<M, TW>::MIN_BLOCKS)) void k_col_apply(
     Ws w, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
     const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, int ngroups,
     float2* __restrict__ dpart, long long dstride) {
-  constexpr int NT = ApplyCfg<M>::NT, E = ApplyCfg<M>::E, T = ApplyCfg<M>::T, TH = ApplyCfg<M>::THREADS;
+  using Cfg = ApplyCfg<M, TW>;
+  constexpr int NT = Cfg::NT, E = Cfg::E, T = Cfg::T, TH = Cfg::THREADS;
   constexpr int TS = T + 2;  // tile stride with the two halo columns
   constexpr int HP = (2 * M + TH - 1) / TH;
   constexpr bool DUAL = ApplyDual<M>::value;
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void k_row_update(Ws w, int mod
     if (st->done) return;
     it = st->it_r;
     // sigma partials: one per column tile (line masks) or row tile (2D masks)
-    const int nrt = sd.m / kRowRR, nct = sd.mask_kind == 0 ? N / col_tile(sd.m) : nrt;
+    const int nrt = sd.m / kRowRR, nct = sd.mask_kind == 0 ? sd.ctiles : nrt;
     const double sigma = part_sum(part_ptr(w.part, s, P_SIGMA), nct);
     const double rho = part_sum(part_ptr(w.part, s, P_RHO0 + (it & 1)), nrt);
     const double a = rho / sigma;
@@ -757,29 +758,44 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, co
 
 // ============================================================== launchers
 
-template <int M, int PH>
+template <int M, int PH, int TW = col_tile(M)>
 void launch_col_apply_phase(dim3 grid, const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
                             int ngroups, float2* dpart, long long dstride) {
-  const dim3 block(ApplyCfg<M>::THREADS);
+  const dim3 block(ApplyCfg<M, TW>::THREADS);
   if (mode == CA_PCG)
-    hipLaunchKernelGGL((k_col_apply<M, CA_PCG, PH>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc, pold,
-                       pn, out, ngroups, dpart, dstride);
+    hipLaunchKernelGGL((k_col_apply<M, CA_PCG, PH, TW>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc,
+                       pold, pn, out, ngroups, dpart, dstride);
   else
-    hipLaunchKernelGGL((k_col_apply<M, CA_APPLY, PH>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc, pold,
-                       pn, out, ngroups, dpart, dstride);
+    hipLaunchKernelGGL((k_col_apply<M, CA_APPLY, PH, TW>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc,
+                       pold, pn, out, ngroups, dpart, dstride);
+}
+
+bool apply_tile_ok(int m, int n, int tile) {
+  if (tile == col_tile(m)) return true;
+  if (tile != apply_tile_alt(m, 0) && tile != apply_tile_alt(m, 1)) return false;
+  return n % tile == 0 && n / tile <= kPartMax;
 }
 
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            int ngroups, float2* dpart, long long dstride) {
+                            int ngroups, float2* dpart, long long dstride, int tile) {
   const int split = (ngroups > 1 && (terms & TERM_DATA)) ? ngroups : 1;
   if (split > 1 && !dpart) return hipErrorInvalidValue;
-  const dim3 grid(L.n / col_tile(L.m), L.count);
+  if (tile == 0) tile = col_tile(L.m);
+  // a coil split runs with the default tiles only
+  if (!apply_tile_ok(L.m, L.n, tile) || (split > 1 && tile != col_tile(L.m))) return hipErrorInvalidValue;
+  const dim3 grid(L.n / tile, L.count);
   switch (L.m) {
 #define PICS_CASE(M)                                                                                            \
   case M:                                                                                                       \
-    if (split == 1) {                                                                                           \
+    if (tile == apply_tile_alt(M, 0)) {                                                                         \
+      launch_col_apply_phase<M, AP_FUSED, apply_tile_alt(M, 0)>(grid, L, w, mode, terms, pk, tol, xin, zsrc,     \
+                                                               pold, pn, out, 1, dpart, dstride);              \
+    } else if (tile == apply_tile_alt(M, 1)) {                                                                  \
+      launch_col_apply_phase<M, AP_FUSED, apply_tile_alt(M, 1)>(grid, L, w, mode, terms, pk, tol, xin, zsrc,     \
+                                                               pold, pn, out, 1, dpart, dstride);              \
+    } else if (split == 1) {                                                                                    \
       launch_col_apply_phase<M, AP_FUSED>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, 1, dpart, \
                                           dstride);                                                            \
     } else {                                                                                                    \

@@ -22,11 +22,19 @@ struct ColCfg {
 // The fused operator's column tiles; lengths up to 256 give each transform
 // exchange its own LDS buffer (two buffers used in turn, so a barrier after
 // reading an exchange is not needed).
-template <int M>
-struct ApplyCfg : ColCfg<M> {
+// TW: columns per tile (the default col_tile(M), or one of the autotuner's
+// alternatives, apply_tile_alt).
+template <int M, int TW = col_tile(M)>
+struct ApplyCfg {
+  static constexpr int NT = Plan<M>::NT;
+  static constexpr int E = M / NT;
+  static constexpr int T = TW;
+  static constexpr int THREADS = NT * T;
   // workgroups per CU the register allocation must allow: two waves per
-  // SIMD at 320 and 512 (4-wave workgroups)
-  static constexpr int MIN_BLOCKS = M == 320 || M == 512 ? 2 : 1;
+  // SIMD at 320 and 512 with the default tiles; the alternative widths ask
+  // for two waves per SIMD as well (at most 256 registers per lane)
+  static constexpr int MIN_BLOCKS = TW == col_tile(M) ? (M == 320 || M == 512 ? 2 : 1)
+                                                      : (512 / THREADS > 0 ? 512 / THREADS : 1);
 };
 template <int M>
 struct ApplyDual { static constexpr bool value = M <= 256; };
