@@ -108,6 +108,25 @@ def run_apply_ragged(torch, B):
         ctx.close()
 
 
+def run_step_mode(torch, B, spec, steps):
+    """One context of ROOFLINE_BATCH headline slices, no autotuning (the
+    batch keeps the default launch shape): preconditioner build + Split
+    Bregman reconstruction, 1 + `steps` times; prints the PCG iterations per
+    reconstruction.  Every kernel of the run belongs to these steps, so
+    whole-run counter totals divided by 1 + steps are per batch
+    reconstruction."""
+    insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(ROOFLINE_BATCH)]
+    ctx, ksp = B.context_for(insts)
+    x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
+    for k in range(1 + steps):
+        ctx.build_preconditioner("circulant")
+        it, _ = ctx.split_bregman_recon(ksp, x, n_outer=20, n_inner=1, tol=1e-3, maxit=1000)
+        print(json.dumps({"reconstruction": k, "slices": ROOFLINE_BATCH, "pcg_iters_total": int(it.sum()),
+                          "pcg_iters_per_solve_mean": round(float(it.mean()), 3)}), flush=True)
+    torch.cuda.synchronize()
+    ctx.close()
+
+
 def run_pcg_mode(torch, ctx, iters=10, reps=5):
     """Iteration-locked PCG solves (every slice runs exactly `iters`
     iterations from x = 0, circulant preconditioner), so that every launch
@@ -557,11 +576,14 @@ def main():
                     help="skip the 512^2 x 32 slice, the ragged batch, the 2D-mask batch and the "
                          "parameter-set comparison")
     ap.add_argument("--train-steps", type=int, default=1500)
-    ap.add_argument("--mode", choices=["full", "apply", "apply2d", "apply_ragged", "pcg", "volume"], default="full",
+    ap.add_argument("--mode", choices=["full", "apply", "apply2d", "apply_ragged", "pcg", "volume", "step"],
+                    default="full",
                     help="apply: only the apply_A timing loop and a copy-kernel calibration (for counter runs); "
                          "apply2d: the same for the 2D-mask operator (256^2 x 12, batch of 32); "
                          "apply_ragged: the ragged 64-slice batch's operator, whole and per size group; "
                          "volume: the 3D section alone; "
+                         "step: 1 + --steps reconstructions of one 128-slice context at the default launch shape "
+                         "(whole-step counter runs); "
                          "pcg: iteration-locked PCG solves over 128 slices (for kernel traces)")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-procs", type=int, default=16,
@@ -600,6 +622,9 @@ def main():
         print(json.dumps(volume_section(torch, B)), flush=True)
         return
     spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=a.scale)
+    if a.mode == "step":
+        run_step_mode(torch, B, spec, a.steps)
+        return
     if a.mode in ("apply", "pcg"):
         insts = [gen.make_instance(spec, gen.eval_seed(2, i)) for i in range(ROOFLINE_BATCH)]
         ctx, _ = B.context_for(insts)
