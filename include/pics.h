@@ -221,12 +221,17 @@ int pics_coil_compress(pics_ctx* ctx, const void* kspace, int32_t nvirt, void* k
 /* Options.
  * PICS_OPT_POLL_CHUNK: PCG iterations enqueued between host convergence polls
  *   (first poll; later polls double it, up to 32).  Default 2.
- * PICS_OPT_GRAPH_BUDGET: split_bregman_recon runs the first outer iteration
- *   host-polled and the others from one captured HIP graph whose PCG solves
- *   carry this many iterations (kernels of converged slices exit at entry).
- *   If a solve needs more, the reconstruction is redone host-polled, so
- *   results never depend on the budget; the context then raises its budget
- *   (to 2, then doubling).  0 disables the graph.  Default 1.
+ * PICS_OPT_GRAPH_BUDGET: split_bregman_recon runs a whole reconstruction
+ *   (initialisation and every outer iteration) from one captured HIP graph
+ *   whose PCG solves carry a fixed number of iterations, this many for every
+ *   solve but the first (kernels of converged slices exit at entry).  If a
+ *   solve needs more, the reconstruction is redone host-polled, so results
+ *   never depend on the budgets; the context then raises the budget that was
+ *   short (to 2, then doubling).  0 disables the graph (every solve
+ *   host-polled).  Default 1.
+ * PICS_OPT_GRAPH_FIRST_BUDGET: the graph's budget for the first solve (from
+ *   the root-sum-of-squares start), 1 .. 256, doubled after a shortfall.
+ *   Default 8.
  * PICS_OPT_COIL_GROUPS: split every column tile's coil loop over this many
  *   workgroups (clamped to each group's coil count), overriding the
  *   autotuner; 1 = no split (the default before pics_autotune).  A split
@@ -248,6 +253,7 @@ int pics_coil_compress(pics_ctx* ctx, const void* kspace, int32_t nvirt, void* k
 #define PICS_OPT_COIL_GROUPS 3
 #define PICS_OPT_CONCURRENT_GROUPS 4
 #define PICS_OPT_COL_TILE 5
+#define PICS_OPT_GRAPH_FIRST_BUDGET 6
 int pics_set_option(pics_ctx* ctx, int32_t key, int64_t value);
 
 /* ---------------------------------------------------------------------------

@@ -30,6 +30,7 @@ OPT_GRAPH_BUDGET = 2
 OPT_COIL_GROUPS = 3
 OPT_CONCURRENT_GROUPS = 4
 OPT_COL_TILE = 5
+OPT_GRAPH_FIRST_BUDGET = 6
 TUNE_FORCE = 1
 TUNE_NO_WRITE = 2
 

@@ -74,6 +74,7 @@ struct pics_ctx {
 
   // Split Bregman outer iterations replayed from a captured graph
   int graph_budget = 1;          // PCG iterations per solve inside the graph (0: host-polled only)
+  int graph_first_budget = 8;    // the same for the first solve (from the root-sum-of-squares start)
   int* solve_counter = nullptr;  // device: history row of the next solve
   int* hist = nullptr;           // device: [solves][nslices] iterations, then [solves][nslices] status
   long long hist_cap = 0;        // ints at hist (2 solves_cap nslices)
@@ -82,13 +83,15 @@ struct pics_ctx {
   hipGraphExec_t graph_exec = nullptr;
   struct GraphKey {
     const void* x;
+    const void* kspace;
     double tol;
-    int budget, pk, n_inner, n_rep;
+    int budget, first_budget, pk, n_inner, n_rep;
     const int* hist;
     int tuning;  // tuning generation: a new coil split or workspace needs a new graph
     bool operator==(const GraphKey& o) const {
-      return x == o.x && tol == o.tol && budget == o.budget && pk == o.pk && n_inner == o.n_inner &&
-             n_rep == o.n_rep && hist == o.hist && tuning == o.tuning;
+      return x == o.x && kspace == o.kspace && tol == o.tol && budget == o.budget &&
+             first_budget == o.first_budget && pk == o.pk && n_inner == o.n_inner && n_rep == o.n_rep &&
+             hist == o.hist && tuning == o.tuning;
     }
   } graph_key{};
   int graph_fallbacks = 0;       // solves that exceeded the budget (reconstruction redone host-polled)
@@ -376,6 +379,11 @@ int pics_set_option(pics_ctx* c, int32_t key, int64_t value) {
   if (key == PICS_OPT_GRAPH_BUDGET) {
     if (value < 0 || value > 64) return fail(c, PICS_ERR_INVALID, "graph budget out of range");
     c->graph_budget = (int)value;
+    return PICS_OK;
+  }
+  if (key == PICS_OPT_GRAPH_FIRST_BUDGET) {
+    if (value < 1 || value > 256) return fail(c, PICS_ERR_INVALID, "first-solve graph budget out of range");
+    c->graph_first_budget = (int)value;
     return PICS_OK;
   }
   if (key == PICS_OPT_CONCURRENT_GROUPS) {
@@ -963,10 +971,42 @@ int enq_outer_iteration_budgeted(pics_ctx* c, float2* x, double tol, int n_inner
   return PICS_OK;
 }
 
-// Capture n_rep outer iterations (all but the first of a reconstruction) as
-// one graph.
-int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget, int n_rep) {
-  const pics_ctx::GraphKey key{x, tol, budget, c->pk, n_inner, n_rep, c->hist, c->tuning_gen};
+// Algorithm 1, step 1 (coil images, root sum of squares, g_1, the first
+// right-hand side) for every slice.
+int enq_sb_init(pics_ctx* c, const float2* kspace, float2* x) {
+  GroupFork fk(c);
+  for (auto& g : c->groups) {
+    HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, kspace, c->coiltmp));
+    HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, c->rhs, x));
+  }
+  HIPCHK(c, fk.join());
+  return PICS_OK;
+}
+
+// The first outer iteration with fixed-budget solves: the first solve (its
+// right-hand side written by the initialisation, r = b - A x0 formed by its
+// set-up) carries first_budget iterations, any further inner solve budget.
+int enq_first_outer_budgeted(pics_ctx* c, float2* x, double tol, int n_inner, int first_budget, int budget) {
+  for (int ji = 0; ji < n_inner; ++ji) {
+    int rc = ji == 0 ? PICS_OK : enq_rhs(c);
+    if (rc) return rc;
+    const int b = ji == 0 ? first_budget : budget;
+    rc = enq_pcg_setup(c, c->rhs, x, tol, b, nullptr, ji > 0);
+    if (rc) return rc;
+    rc = enq_pcg_iters(c, x, tol, 0, b);
+    if (rc) return rc;
+    const SolveRecord rec{c->hist, c->hist + c->hist_cap / 2, c->solve_counter, tol, c->nslices};
+    rc = enq_shrinks(c, x, ji == n_inner - 1, ji, rec);
+    if (rc) return rc;
+  }
+  return PICS_OK;
+}
+
+// Capture a whole reconstruction -- the initialisation, the first outer
+// iteration and the n_rep outer iterations after it -- as one graph.
+int sb_graph(pics_ctx* c, const float2* kspace, float2* x, double tol, int n_inner, int first_budget, int budget,
+             int n_rep) {
+  const pics_ctx::GraphKey key{x, kspace, tol, budget, first_budget, c->pk, n_inner, n_rep, c->hist, c->tuning_gen};
   if (c->graph_exec && c->graph_key == key) return PICS_OK;
   if (c->graph_exec) {
     HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
@@ -978,7 +1018,8 @@ int sb_graph(pics_ctx* c, float2* x, double tol, int n_inner, int budget, int n_
   int rc;
   {
     StreamSwap sw(c, c->cap_stream);
-    rc = PICS_OK;
+    rc = enq_sb_init(c, kspace, x);
+    if (rc == PICS_OK) rc = enq_first_outer_budgeted(c, x, tol, n_inner, first_budget, budget);
     for (int k = 0; k < n_rep && rc == PICS_OK; ++k)
       rc = enq_outer_iteration_budgeted(c, x, tol, n_inner, budget, 1 + k);
   }
@@ -1046,53 +1087,15 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
   }
   float2* x = (float2*)x_out;
   const bool use_graph = !lock_iters && c->graph_budget > 0 && n_outer > 1 && tol > 0.0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    const bool graph_now = use_graph && attempt == 0;
-    // Algorithm 1, step 1: coil images F^H R y_i, root sum of squares, g_1
-    {
-      GroupFork fk(c);
-      for (auto& g : c->groups) {
-        HIPCHK(c, launch_row_fft(make_launch(c, g), ws_for(c, g), 1, 1, (const float2*)kspace, c->coiltmp));
-        HIPCHK(c, launch_col_sb_init(make_launch(c, g), ws_for(c, g), c->coiltmp, c->g1, c->g, c->rhs, x));
-      }
-      HIPCHK(c, fk.join());
-    }
-    // b_x = b_y = b_w = 0 and d = 0 at the start: the first right-hand side
-    // is g (written by the initialisation) and the first shrinks read no
-    // Bregman variables
-    bool q_valid = false;
-    int rc_all = PICS_OK;
-    const int host_outer = graph_now ? 1 : n_outer;
-    for (int jo = 0; jo < host_outer; ++jo) {
-      for (int ji = 0; ji < n_inner; ++ji) {
-        const long long solve = (long long)jo * n_inner + ji;
-        int rc = solve == 0 ? PICS_OK : enq_rhs(c);
-        if (rc) return rc;
-        if (lock_iters) {
-          int mx = 0;
-          for (int s = 0; s < c->nslices; ++s) mx = std::max(mx, (int)lock_iters[solve * c->nslices + s]);
-          rc = pcg_run(c, c->rhs, x, 0.0, 0, c->lock_dev + solve * c->nslices, mx, q_valid);
-        } else {
-          rc = pcg_run(c, c->rhs, x, tol, maxit, nullptr, maxit, q_valid);
-        }
-        if (rc < 0) return rc;
-        if (rc > 0) rc_all = rc;
-        if (pcg_iters)
-          for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
-        rc = enq_shrinks(c, x, ji == n_inner - 1, solve);
-        if (rc) return rc;
-        q_valid = true;  // the shrinks left A x = b - r in q
-      }
-    }
-    if (!graph_now) {
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      return rc_all;
-    }
-    // outer iterations 2 .. n_outer from the captured graph
+  if (use_graph) {
+    // the whole reconstruction from one graph: fixed-budget solves whose
+    // kernels exit at entry once a slice has converged, and a device record
+    // of every solve's count and status
     const int budget = std::min(c->graph_budget, maxit);
-    int rc = sb_graph(c, x, tol, n_inner, budget, n_outer - 1);
+    const int first_budget = std::min(c->graph_first_budget, maxit);
+    int rc = sb_graph(c, (const float2*)kspace, x, tol, n_inner, first_budget, budget, n_outer - 1);
     if (rc) return rc;
-    HIPCHK(c, launch_set_int(c->stream, c->solve_counter, n_inner));
+    HIPCHK(c, launch_set_int(c->stream, c->solve_counter, 0));
     HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
     const long long rows = nsolve * c->nslices;
     c->hist_host.resize(2 * rows);
@@ -1100,24 +1103,56 @@ int split_bregman_recon(pics_ctx* c, const void* kspace, int32_t n_outer, int32_
     HIPCHK(c, hipMemcpyAsync(c->hist_host.data() + rows, c->hist + c->hist_cap / 2, sizeof(int) * rows,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    bool over_budget = false;
-    for (long long r = (long long)n_inner * c->nslices; r < rows; ++r) {
-      const int st = c->hist_host[rows + r];
-      if (st < 0) return fail(c, st, "PCG failed inside the outer-iteration graph: %s", pics_status_string(st));
-      if (st == 0) over_budget = true;
-    }
-    if (!over_budget) {
-      if (pcg_iters)
-        for (long long r = (long long)n_inner * c->nslices; r < rows; ++r) pcg_iters[r] = c->hist_host[r];
-      return rc_all;
-    }
-    // a solve needed more than the budget: redo the reconstruction host-polled
+    bool over_first = false, over = false;
     int mx = 0;
-    for (long long r = (long long)n_inner * c->nslices; r < rows; ++r) mx = std::max(mx, c->hist_host[r]);
-    c->graph_budget = std::min(64, std::max(c->graph_budget < 2 ? 2 : c->graph_budget * 2, mx + 1));
+    for (long long r = 0; r < rows; ++r) {
+      const int st = c->hist_host[rows + r];
+      if (st < 0) return fail(c, st, "PCG failed inside the reconstruction graph: %s", pics_status_string(st));
+      if (st == 0) (r < c->nslices ? over_first : over) = true;
+      if (r >= c->nslices) mx = std::max(mx, c->hist_host[r]);
+    }
+    if (!over_first && !over) {
+      if (pcg_iters)
+        for (long long r = 0; r < rows; ++r) pcg_iters[r] = c->hist_host[r];
+      return PICS_OK;
+    }
+    // a solve needed more than its budget: redo the reconstruction
+    // host-polled (results never depend on the budgets) and raise the budget
+    if (over_first) c->graph_first_budget = std::min(256, 2 * c->graph_first_budget);
+    if (over) c->graph_budget = std::min(64, std::max(c->graph_budget < 2 ? 2 : c->graph_budget * 2, mx + 1));
     c->graph_fallbacks++;
   }
-  return PICS_OK;
+  // host-polled: Algorithm 1, step 1, then every solve polled to convergence
+  int rc = enq_sb_init(c, (const float2*)kspace, x);
+  if (rc) return rc;
+  // b_x = b_y = b_w = 0 and d = 0 at the start: the first right-hand side
+  // is g (written by the initialisation) and the first shrinks read no
+  // Bregman variables
+  bool q_valid = false;
+  int rc_all = PICS_OK;
+  for (int jo = 0; jo < n_outer; ++jo) {
+    for (int ji = 0; ji < n_inner; ++ji) {
+      const long long solve = (long long)jo * n_inner + ji;
+      rc = solve == 0 ? PICS_OK : enq_rhs(c);
+      if (rc) return rc;
+      if (lock_iters) {
+        int mx = 0;
+        for (int s = 0; s < c->nslices; ++s) mx = std::max(mx, (int)lock_iters[solve * c->nslices + s]);
+        rc = pcg_run(c, c->rhs, x, 0.0, 0, c->lock_dev + solve * c->nslices, mx, q_valid);
+      } else {
+        rc = pcg_run(c, c->rhs, x, tol, maxit, nullptr, maxit, q_valid);
+      }
+      if (rc < 0) return rc;
+      if (rc > 0) rc_all = rc;
+      if (pcg_iters)
+        for (int s = 0; s < c->nslices; ++s) pcg_iters[solve * c->nslices + s] = c->st_host[s].iters;
+      rc = enq_shrinks(c, x, ji == n_inner - 1, solve);
+      if (rc) return rc;
+      q_valid = true;  // the shrinks left A x = b - r in q
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return rc_all;
 }
 
 }  // extern "C"

@@ -78,6 +78,7 @@ def test_binding_constants_match_header():
     assert d["PICS_OPT_COIL_GROUPS"] == B.OPT_COIL_GROUPS
     assert d["PICS_OPT_CONCURRENT_GROUPS"] == B.OPT_CONCURRENT_GROUPS
     assert d["PICS_OPT_COL_TILE"] == B.OPT_COL_TILE
+    assert d["PICS_OPT_GRAPH_FIRST_BUDGET"] == B.OPT_GRAPH_FIRST_BUDGET
     assert d["PICS_TUNE_FORCE"] == B.TUNE_FORCE
     assert d["PICS_TUNE_NO_WRITE"] == B.TUNE_NO_WRITE
 

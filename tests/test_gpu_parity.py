@@ -355,6 +355,17 @@ def test_split_bregman_graph_equals_host_polled(torch, B, scale):
     _, _, x_small, it_small = _sb_run(torch, B, insts, budget=1)
     assert np.array_equal(it_small, it_ref)
     assert np.array_equal(_host(x_small), ref)
+    # a first-solve budget below the first solve's count: the whole-graph run
+    # falls back, and the next call runs from the graph with the raised budget
+    ctx2, ksp2 = _ctx(B, insts)
+    ctx2.set_option(B.OPT_GRAPH_BUDGET, 4)
+    ctx2.set_option(B.OPT_GRAPH_FIRST_BUDGET, 1)
+    ctx2.build_preconditioner("circulant")
+    for rep in range(3):
+        x3 = torch.zeros(ctx2.image_elems, dtype=torch.complex64, device="cuda")
+        it3, _ = ctx2.split_bregman_recon(ksp2, x3, n_outer=8, tol=1e-3, maxit=1000)
+        assert np.array_equal(it3, it_ref), rep
+        assert np.array_equal(_host(x3), ref), rep
 
 
 # ---------------------------------------------------------------- coil split
