@@ -44,6 +44,30 @@ def apply_bytes(specs) -> int:
     return int(sum(8 * s.m * s.n * (s.ncoils + 2) for s in specs))
 
 
+def reconstruction_bytes(spec, pcg_iters: int, n_outer: int = 20) -> int:
+    """Algorithmic HBM bytes of one slice's Split Bregman reconstruction with
+    the circulant preconditioner (build included, n_inner = 1), from each
+    kernel's reads and writes of image- and coil-shaped arrays (8 bytes per
+    complex64 element, 4 per float), given the slice's total PCG iterations:
+      build            (8 N_c + 20) N   coil maps, coil energy, k and 1/k
+      initialisation   (24 N_c f + 8 N_c + 32) N   sampled k-space rows (f of
+                       them) through the row pass, coil maps, g_1 g rhs x
+      first set-up     (8 N_c + 92) N   operator on x_0, row / column / row pass
+      later set-ups    76 N each        r = b - q, M^-1 r
+      shrinks          (140 + sum_l 44 / 4^l) N per outer iteration: level-0
+                       analysis with TV shrink and outer update 116, level-0
+                       synthesis 24, coarser levels l = 1.. 28 + 16 per 4^l
+      PCG iteration    (8 N_c + 132) N  operator 8 N_c + 32, row pass 56,
+                       column pass 20, row pass 24"""
+    N = spec.m * spec.n
+    C = spec.ncoils
+    f = round(spec.m / spec.accel) / spec.m
+    coarse = sum(44.0 / 4 ** l for l in range(1, spec.levels)) if spec.levels > 0 else 0.0
+    per_px = ((8 * C + 20) + (24 * C * f + 8 * C + 32) + (8 * C + 92) + 76 * (n_outer - 1)
+              + n_outer * (140 + coarse) + pcg_iters * (8 * C + 132))
+    return int(per_px * N)
+
+
 def time_apply_kernel(torch, ctx, xd, yd, reps=50, terms=None):
     """Average duration of apply_A (by default the fused operator kernel), from
     HIP events recorded on the library's stream around `reps` back-to-back
@@ -700,6 +724,9 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     iters = runs[0]["iters"]
+    # the step's algorithmic bytes: every slice's reconstruction with its own
+    # PCG iteration count (last timed step of each context)
+    step_bytes = sum(reconstruction_bytes(spec, int(it)) for r in runs for it in r["iters"].sum(axis=0))
     step_ms = np.array(per_ctx_ms).ravel()
     value = a.batch * a.steps / dt
     ms_per_step = dt / a.steps * 1e3
@@ -852,6 +879,13 @@ def main():
                                 else f"k_col_apply<256, 0, 1> + <256, 0, 2> (apply_A, coil split {rsplit[0]})"),
                      "avg_us": round(t_apply * 1e6, 2), "bytes_per_launch": bytes_apply,
                      "valu": valu_roofline(t_apply) if (rsplit[0], rtile[0]) == (1, 16) else None},
+        "step_roofline": {"bound": "hbm", "achieved": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "bytes_per_step": step_bytes,
+                          "note": "whole step: algorithmic bytes of every slice's reconstruction (build, "
+                                  "initialisation, set-ups, PCG iterations at their measured counts, shrinks) "
+                                  "over the step's wall time"},
         "apply_A_explicit_wavelet": {"avg_us": round(t_explicit * 1e6, 2),
                                      "vs_fused": round(t_explicit / t_apply, 3),
                                      "note": f"{ROOFLINE_BATCH} slices; gamma W^H W through the 3-level db4 analysis "

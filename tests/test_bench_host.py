@@ -64,3 +64,14 @@ def test_all_cores_oracle_baseline_sums_the_workers():
     r = bench.cpu_baseline_all_cores(2, seconds=0.1)
     assert r["cores"] == 2 and r["count"] >= 2
     assert 0 < r["value"] <= r["count"] / min(0.1, r["seconds"]) and r["unit"] == "recons/s"
+
+
+def test_reconstruction_bytes_per_pixel():
+    """The whole-step byte model at the headline slice: 5023 bytes per pixel
+    with no PCG iteration (build 116, initialisation 200, first set-up 188,
+    19 later set-ups 1444, 20 shrink passes 3075) and 228 per iteration."""
+    spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3)
+    N = 256 * 256
+    assert bench.reconstruction_bytes(spec, 0) == 5023 * N
+    assert bench.reconstruction_bytes(spec, 10) - bench.reconstruction_bytes(spec, 0) == 2280 * N
+    assert bench.reconstruction_bytes(spec, 0, n_outer=1) == (116 + 200 + 188 + 153.75) * N
