@@ -68,22 +68,32 @@ def reconstruction_bytes(spec, pcg_iters: int, n_outer: int = 20) -> int:
     return int(per_px * N)
 
 
+def hold_stream(torch, stream, cycles=100_000_000):
+    """Enqueue a spin kernel (tens of milliseconds at the counter rate seen
+    on MI355X, about 3.6e6 counts per ms) on `stream`, so that the work
+    enqueued behind it runs back to back however slowly the host submits it."""
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(int(cycles))
+
+
 def time_apply_kernel(torch, ctx, xd, yd, reps=50, terms=None):
-    """Average duration of apply_A (by default the fused operator kernel), from
-    HIP events recorded on the library's stream around `reps` back-to-back
-    calls."""
+    """Average duration of one apply_A launch (by default the fused operator
+    kernel): a pair of HIP events recorded on the library's stream around
+    each of `reps` calls, enqueued behind a spin kernel so that they run back
+    to back on the GPU; the per-launch elapsed times are averaged (the gaps
+    between launches are not counted)."""
     stream = torch.cuda.ExternalStream(ctx.stream) if ctx.stream else torch.cuda.current_stream()
     kw = {} if terms is None else {"terms": terms}
     for _ in range(5):
         ctx.apply_A(xd, yd, **kw)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    hold_stream(torch, stream)
+    for e0, e1 in ev:
+        e0.record(stream)
         ctx.apply_A(xd, yd, **kw)
-    e1.record(stream)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps * 1e-3  # seconds
+        e1.record(stream)
+    ev[-1][1].synchronize()
+    return sum(e0.elapsed_time(e1) for e0, e1 in ev) / reps * 1e-3  # seconds
 
 
 COPY_CAL_BYTES = 256 * 2**20
