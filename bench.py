@@ -77,8 +77,8 @@ def hold_stream(torch, stream, cycles=100_000_000):
 
 
 def time_apply_kernel(torch, ctx, xd, yd, reps=50, terms=None):
-    """Average duration of one apply_A launch (by default the fused operator
-    kernel): a pair of HIP events recorded on the library's stream around
+    """Average duration of one apply_A call (for a slice context one launch
+    of the fused operator kernel): a pair of HIP events recorded on the library's stream around
     each of `reps` calls, enqueued behind a spin kernel so that they run back
     to back on the GPU; the per-launch elapsed times are averaged (the gaps
     between launches are not counted)."""
@@ -475,23 +475,23 @@ def volume_section(torch, B):
         out[kind] = {"pcg_iters": it, "relres": rel, "solve_s": round(time.perf_counter() - t0, 4),
                      "build_s": round(tb, 4)}
     y = torch.empty_like(b)
-    for _ in range(2):
-        vol.apply_A(b, y)
-    st = torch.cuda.ExternalStream(vol.stream) if vol.stream else torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    e0.record(st)
-    for _ in range(reps):
-        vol.apply_A(b, y)
-    e1.record(st)
-    e1.synchronize()
-    t_apply = e0.elapsed_time(e1) / reps * 1e-3
+    # one operator application (all its x chunks and passes) per timed call,
+    # at every admissible chunk width and at the automatic one
+    sweep = {}
+    for X in [c for c in range(16, spec.n + 1, 16) if spec.n % c == 0] + [0]:
+        vol.set_option(B.OPT3_XCHUNK, X)
+        sweep[X or "auto"] = time_apply_kernel(torch, vol, b, y, reps=10)
+    X = vol.get_option(B.OPT3_XCHUNK)
+    t_apply = sweep["auto"]
     floor = 8 * spec.p * spec.m * spec.n * (spec.ncoils + 2)
     out["apply_A_ms"] = round(t_apply * 1e3, 3)
+    out["x_chunk"] = X
+    out["apply_A_ms_per_x_chunk"] = {str(k): round(v * 1e3, 3) for k, v in sweep.items()}
     out["apply_roofline"] = {"bound": "hbm", "achieved": round(floor / t_apply / 1e9, 1), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(floor / t_apply / 1e9 / HBM_PEAK_GBS, 4),
                              "bytes_per_launch": floor,
-                             "note": "algorithmic floor 8 V (N_c + 2): read x and the coil maps, write y"}
+                             "note": "algorithmic floor 8 V (N_c + 2): read x and the coil maps, write y; "
+                                     "one application = three passes per x chunk"}
     vol.close()
     return out
 

@@ -372,6 +372,17 @@ int pics3d_apply_Minv(pics3d_ctx* ctx, const void* r, void* z);
 int pics3d_pcg_solve(pics3d_ctx* ctx, const void* b, void* x, double tol, int32_t maxit, int32_t* iters,
                      double* relres);
 const char* pics3d_last_error(const pics3d_ctx* ctx);
+/* Options of a 3D context.  PICS3D_OPT_XCHUNK: for masks constant along x the
+ * operator runs in chunks of X columns of the x axis, each through three
+ * passes over a chunk workspace [nc][p][m][X] (kept small enough to stay in
+ * the last-level cache between its passes); value: X, a multiple of the
+ * column tile of the m axis (16 up to m = 320, 4 at 512, 8 at 1024) that
+ * divides n, or 0 for the widest X whose workspace is at most 128 MiB
+ * (PICS_ERR_INVALID otherwise).  get_option gives the X in use (0 when the
+ * mask varies along x and the operator takes the full 3D transforms). */
+#define PICS3D_OPT_XCHUNK 1
+int pics3d_set_option(pics3d_ctx* ctx, int32_t option, int32_t value);
+int pics3d_get_option(const pics3d_ctx* ctx, int32_t option, int32_t* value);
 
 #ifdef __cplusplus
 }

@@ -33,6 +33,7 @@ OPT_COL_TILE = 5
 OPT_GRAPH_FIRST_BUDGET = 6
 TUNE_FORCE = 1
 TUNE_NO_WRITE = 2
+OPT3_XCHUNK = 1
 
 
 class PicsError(RuntimeError):
@@ -99,6 +100,8 @@ def signatures():
         "pics3d_apply_Minv": (ctypes.c_int, [vp, vp, vp]),
         "pics3d_pcg_solve": (ctypes.c_int, [vp, vp, vp, dbl, i32, pi32, pdbl]),
         "pics3d_last_error": (ctypes.c_char_p, [vp]),
+        "pics3d_set_option": (ctypes.c_int, [vp, i32, i32]),
+        "pics3d_get_option": (ctypes.c_int, [vp, i32, pi32]),
     }
 
 
@@ -410,6 +413,14 @@ class Volume:
 
     def rhs(self, kspace, b) -> int:
         return self._check(self.L.pics3d_rhs(self.h, _ptr(kspace), _ptr(b)))
+
+    def set_option(self, option: int, value: int) -> int:
+        return self._check(self.L.pics3d_set_option(self.h, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int32()
+        self._check(self.L.pics3d_get_option(self.h, int(option), ctypes.byref(v)))
+        return v.value
 
     def pcg_solve(self, b, x, tol: float, maxit: int):
         it = ctypes.c_int32()

@@ -33,6 +33,7 @@ struct pics3d_ctx {
   int* idx;  // 0, 1, 2, ... (grid.y -> slice)
   bool built = false;
   bool xconst = false;  // mask constant along x: the operator's three-pass (z, y) path
+  int xchunk_opt = 0;    // PICS3D_OPT_XCHUNK (0: automatic)
   char err[256] = {0};
 };
 
@@ -83,15 +84,40 @@ int fft3(pics3d_ctx* c, float2* buf, int count, int inverse, float2* scratch) {
   return PICS_OK;
 }
 
+// x-chunk width of the x-constant operator: the option if set, else the
+// widest chunk (a multiple of the m axis' column tile dividing n) whose coil
+// workspace [nc][p][m][X] fits kVolChunkBytes, half the 256 MiB last-level
+// cache (the chunk's coil maps, read by the first and the last pass, take
+// the other half)
+constexpr long long kVolChunkBytes = 128ll << 20;
+int xchunk(const pics3d_ctx* c) {
+  if (c->xchunk_opt > 0) return c->xchunk_opt;
+  const int T = col_tile(c->d.m), n = c->d.n;
+  const long long per_col = (long long)c->d.ncoils * c->d.p * c->d.m * (long long)sizeof(float2);
+  int best = T;
+  for (int X = T; X <= n; X += T)
+    if (n % X == 0 && per_col * X <= kVolChunkBytes) best = X;
+  return best;
+}
+
+bool xchunk_ok(const pics3d_ctx* c, int X) {
+  const int T = col_tile(c->d.m);
+  return X >= T && X <= c->d.n && X % T == 0 && c->d.n % X == 0;
+}
+
 int apply3(pics3d_ctx* c, const float2* x, float2* y) {
   const int nc = c->d.ncoils;
   if (c->xconst) {
-    // F^H R F = (F_zy^H R_zy F_zy) (x) I_x: transforms along y and z only
-    const int p = c->d.p, m = c->d.m, n = c->d.n;
-    HIPCHK3(c, launch3_col_sp(c->stream, c->sens, x, c->coil, c->tw, nc, p, m, n));
-    HIPCHK3(c, launch3_col_z(c->stream, c->coil, c->mask, c->tw, nc, p, m, n, (float)(1.0 / ((double)p * m))));
-    HIPCHK3(c, launch3_col_acc(c->stream, c->sens, c->coil, x, y, c->tw, nc, p, m, n, (float)c->d.mu,
-                               (float)c->d.lambda, (float)c->d.gamma, 1));
+    // F^H R F = (F_zy^H R_zy F_zy) (x) I_x: transforms along y and z only,
+    // chunk by chunk along x through one chunk-sized workspace
+    const int p = c->d.p, m = c->d.m, n = c->d.n, X = xchunk(c);
+    const float scale = (float)(1.0 / ((double)p * m));
+    for (int x0 = 0; x0 < n; x0 += X) {
+      HIPCHK3(c, launch3_col_sp(c->stream, c->sens, x, c->coil, c->tw, nc, p, m, n, x0, X));
+      HIPCHK3(c, launch3_col_z(c->stream, c->coil, c->mask, c->tw, nc, p, m, n, x0, X, scale));
+      HIPCHK3(c, launch3_col_acc(c->stream, c->sens, c->coil, x, y, c->tw, nc, p, m, n, (float)c->d.mu,
+                                 (float)c->d.lambda, (float)c->d.gamma, 1, x0, X));
+    }
     return PICS_OK;
   }
   HIPCHK3(c, launch3_coil_mul(c->stream, c->sens, x, c->coil, nc, c->V));
@@ -218,6 +244,23 @@ int pics3d_destroy(pics3d_ctx* c) {
 }
 
 const char* pics3d_last_error(const pics3d_ctx* c) { return c ? c->err : "null context"; }
+
+int pics3d_set_option(pics3d_ctx* c, int32_t option, int32_t value) {
+  if (!c) return PICS_ERR_INVALID;
+  if (option != PICS3D_OPT_XCHUNK) return fail3(c, PICS_ERR_INVALID, "set_option: unknown option %d", option);
+  if (value != 0 && !xchunk_ok(c, value))
+    return fail3(c, PICS_ERR_INVALID, "set_option: x chunk %d must be a multiple of %d dividing %d", value,
+                 col_tile(c->d.m), c->d.n);
+  c->xchunk_opt = value;
+  return PICS_OK;
+}
+
+int pics3d_get_option(const pics3d_ctx* c, int32_t option, int32_t* value) {
+  if (!c || !value) return PICS_ERR_INVALID;
+  if (option != PICS3D_OPT_XCHUNK) return PICS_ERR_INVALID;
+  *value = c->xconst ? xchunk(c) : 0;
+  return PICS_OK;
+}
 
 int pics3d_apply_A(pics3d_ctx* c, const void* x, void* y) {
   if (!c) return PICS_ERR_INVALID;

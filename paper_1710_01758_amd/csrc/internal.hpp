@@ -219,13 +219,16 @@ hipError_t launch3_corr_mul(hipStream_t st, float2* a, const float2* b, long lon
 hipError_t launch3_build_k(hipStream_t st, const float2* a, float* kraw, float* kinv, int* bad, int p, int m, int n,
                            double mu, double lam, double gam);
 hipError_t launch3_scale(hipStream_t st, float2* buf, const float* s, long long V);
-// operator passes for masks constant along x (see k_volume.hip)
+// operator passes for masks constant along x over the chunk of columns
+// x0 .. x0 + X - 1 (X a multiple of col_tile(m) dividing n; the chunk
+// workspace `coil` is [nc][p][m][X]; see k_volume.hip)
 hipError_t launch3_col_sp(hipStream_t st, const float2* S, const float2* x, float2* coil, const float2* tw, int nc,
-                          int p, int m, int n);
+                          int p, int m, int n, int x0, int X);
 hipError_t launch3_col_z(hipStream_t st, float2* coil, const uint8_t* mask, const float2* tw, int nc, int p, int m,
-                         int n, float scale);
+                         int n, int x0, int X, float scale);
 hipError_t launch3_col_acc(hipStream_t st, const float2* S, const float2* coil, const float2* x, float2* y,
-                           const float2* tw, int nc, int p, int m, int n, float mu, float lam, float gam, int data);
+                           const float2* tw, int nc, int p, int m, int n, float mu, float lam, float gam, int data,
+                           int x0, int X);
 hipError_t launch3_xconst(hipStream_t st, const uint8_t* mask, long long rows, int n, int* flag);
 // scal[idx] = Re(a^H b) in FP64 (partials in part[slot][kVolDotBlocks], fixed-order sum)
 hipError_t launch3_dot(hipStream_t st, const float2* a, const float2* b, long long V, double* part, int slot,

@@ -108,26 +108,31 @@ __global__ __launch_bounds__(256) void k3_scale(float2* __restrict__ buf, const 
 // variable-density pattern over (z, y) with x fully sampled).  Then the 3D
 // data term factors as F^H R F = (F_zy^H R_zy F_zy) (x) I_x: each coil needs
 // transforms along y and z only, and x is the contiguous batch axis of every
-// pass.  Three passes over the coil workspace [nc][p][m][n]:
+// pass.  The x axis is taken in chunks of X columns (x0 .. x0 + X - 1); each
+// chunk runs three passes over a chunk workspace [nc][p][m][X]:
 //   1. y-columns of each plane:  u_c = F_y (S_c x)                     (k3_col_sp)
 //   2. z-columns of each coil:   u_c = F_z^H (r / (p m)) F_z u_c        (k3_col_z)
 //   3. y-columns of each plane:  y = mu sum_c conj(S_c) F_y^H u_c
 //                                    + lam (D_z^H D_z + D_y^H D_y + D_x^H D_x) x + gam x  (k3_col_acc)
-// Each column workgroup owns T adjacent x columns of one plane (passes 1, 3)
-// or of the flattened (y, x) index (pass 2) and the whole transform length.
+// A chunk's workspace is sized to stay in the last-level cache between its
+// passes (the next chunk reuses the same lines).  Each column workgroup owns
+// T adjacent x columns of one plane (passes 1, 3) or of the flattened (y, x)
+// index of the chunk (pass 2) and the whole transform length.
 // ----------------------------------------------------------------------------
 template <int M>
 __global__ __launch_bounds__(ColCfg<M>::THREADS) void k3_col_sp(const float2* __restrict__ S,
                                                                 const float2* __restrict__ x,
                                                                 float2* __restrict__ coil,
                                                                 const float2* __restrict__ tw, int nc, int n,
-                                                                long long V) {
+                                                                long long V, int x0, int X) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T, TH = ColCfg<M>::THREADS;
   __shared__ float2 lds[ColLay<T>::template size<M>];
   __shared__ float2 s_tw[M];
   const int j = threadIdx.x % T, t = threadIdx.x / T;
-  const long long base =
-      (long long)blockIdx.y * M * n + (long long)xcd_tile(blockIdx.x, gridDim.x) * T + j + (long long)t * n;
+  const int jc = xcd_tile(blockIdx.x, gridDim.x) * T + j;  // column within the chunk
+  const long long base = (long long)blockIdx.y * M * n + x0 + jc + (long long)t * n;
+  const long long VC = (long long)gridDim.y * M * X;  // one coil's chunk workspace
+  const long long cbase = (long long)blockIdx.y * M * X + jc + (long long)t * X;
   stage_twiddles<M, TH>(s_tw, tw);
   float2 xv[E], sv[E], sn[E];
 #pragma unroll
@@ -146,36 +151,41 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k3_col_sp(const float2* __
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cmul(sv[e], xv[e]);
     fft<M, -1, ColLay<T>>(v, t, lds, j, s_tw);
+    float2* __restrict__ o = coil + (long long)c * VC + cbase;
 #pragma unroll
-    for (int e = 0; e < E; ++e) coil[off + (long long)NT * e * n] = v[e];
+    for (int e = 0; e < E; ++e) o[(long long)NT * e * X] = v[e];
 #pragma unroll
     for (int e = 0; e < E; ++e) sv[e] = sn[e];
   }
 }
 
+// grid.y = coil; the chunk workspace of one coil is [P][m][X], a z-column is
+// one (y, x) index of the chunk
 template <int P>
 __global__ __launch_bounds__(ColCfg<P>::THREADS) void k3_col_z(float2* __restrict__ coil,
                                                                const uint8_t* __restrict__ mask,
-                                                               const float2* __restrict__ tw, long long mn,
-                                                               long long V, float scale) {
+                                                               const float2* __restrict__ tw, int n, int x0, int X,
+                                                               long long mX, float scale) {
   constexpr int NT = ColCfg<P>::NT, E = ColCfg<P>::E, T = ColCfg<P>::T, TH = ColCfg<P>::THREADS;
   __shared__ float2 lds[ColLay<T>::template size<P>];
   __shared__ float2 s_tw[P];
   const int j = threadIdx.x % T, t = threadIdx.x / T;
-  const long long col = (long long)xcd_tile(blockIdx.x, gridDim.x) * T + j;  // (y, x) index in a plane
-  float2* __restrict__ cb = coil + (long long)blockIdx.y * V + col;
+  const long long col = (long long)xcd_tile(blockIdx.x, gridDim.x) * T + j;  // (y, x) index in the chunk
+  const long long mn = mX / X * n;                                           // one plane of the mask
+  const long long mcol = (col / X) * n + x0 + col % X;                       // the same index in the mask
+  float2* __restrict__ cb = coil + (long long)blockIdx.y * P * mX + col;
   stage_twiddles<P, TH>(s_tw, tw);
   float2 v[E];
   float sc[E];  // r(z, y) / (p m): the pair's scale folded into the mask
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    v[e] = cb[(long long)(t + NT * e) * mn];
-    sc[e] = mask[(long long)(t + NT * e) * mn + col] ? scale : 0.f;
+    v[e] = cb[(long long)(t + NT * e) * mX];
+    sc[e] = mask[(long long)(t + NT * e) * mn + mcol] ? scale : 0.f;
   }
   fft<P, -1, ColLay<T>>(v, t, lds, j, s_tw);
   fft_in_scaled<P, +1, ColLay<T>, false>(v, sc, t, lds, lds, j, s_tw);
 #pragma unroll
-  for (int e = 0; e < E; ++e) cb[(long long)(t + NT * e) * mn] = v[e];
+  for (int e = 0; e < E; ++e) cb[(long long)(t + NT * e) * mX] = v[e];
 }
 
 template <int M>
@@ -192,16 +202,19 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k3_col_acc(const float2* _
                                                                  const float2* __restrict__ x, float2* __restrict__ y,
                                                                  const float2* __restrict__ tw, int nc, int p, int n,
                                                                  long long V, float mu, float lam, float gam,
-                                                                 int data) {
+                                                                 int data, int x0, int X) {
   constexpr int NT = ColCfg<M>::NT, E = ColCfg<M>::E, T = ColCfg<M>::T, TH = ColCfg<M>::THREADS;
   constexpr int TS = Acc3Cfg<M>::TS;
   __shared__ float2 lds[Acc3Cfg<M>::LDS];
   __shared__ float2 s_tw[M];
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int w = blockIdx.y;
-  const int j0 = xcd_tile(blockIdx.x, gridDim.x) * T;
+  const int jc0 = xcd_tile(blockIdx.x, gridDim.x) * T;  // tile start within the chunk
+  const int j0 = x0 + jc0;                              // and in the volume
   const long long pl = (long long)M * n;
   const long long base = (long long)w * pl + j0 + j + (long long)t * n;
+  const long long VC = (long long)p * M * X;
+  const long long cbase = (long long)w * M * X + jc0 + j + (long long)t * X;
   stage_twiddles<M, TH>(s_tw, tw);
   float2 acc[E];
 #pragma unroll
@@ -211,14 +224,15 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k3_col_acc(const float2* _
     float2 v[E], vn[E], sv[E], sn[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      v[e] = coil[base + (long long)NT * e * n];
+      v[e] = coil[cbase + (long long)NT * e * X];
       sv[e] = S[base + (long long)NT * e * n];
     }
     for (int c = 0; c < nc; ++c) {
-      const long long nx = (long long)(c + 1 < nc ? c + 1 : c) * V + base;
+      const int cn = c + 1 < nc ? c + 1 : c;
+      const long long nx = (long long)cn * V + base, ncx = (long long)cn * VC + cbase;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        vn[e] = coil[nx + (long long)NT * e * n];
+        vn[e] = coil[ncx + (long long)NT * e * X];
         sn[e] = S[nx + (long long)NT * e * n];
       }
       fft<M, +1, ColLay<T>>(v, t, lds, j, s_tw);
@@ -377,13 +391,13 @@ hipError_t launch3_update_p(hipStream_t st, float2* p, const float2* z, const do
 
 
 hipError_t launch3_col_sp(hipStream_t st, const float2* S, const float2* x, float2* coil, const float2* tw, int nc,
-                          int p, int m, int n) {
+                          int p, int m, int n, int x0, int X) {
   const long long V = (long long)p * m * n;
-  const dim3 grid(n / col_tile(m), p);
+  const dim3 grid(X / col_tile(m), p);
   switch (m) {
-#define PICS_CASE(M)                                                                                            \
-  case M:                                                                                                       \
-    hipLaunchKernelGGL(k3_col_sp<M>, grid, dim3(ColCfg<M>::THREADS), 0, st, S, x, coil, tw, nc, n, V);          \
+#define PICS_CASE(M)                                                                                         \
+  case M:                                                                                                    \
+    hipLaunchKernelGGL(k3_col_sp<M>, grid, dim3(ColCfg<M>::THREADS), 0, st, S, x, coil, tw, nc, n, V, x0, X); \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE
@@ -394,13 +408,13 @@ hipError_t launch3_col_sp(hipStream_t st, const float2* S, const float2* x, floa
 }
 
 hipError_t launch3_col_z(hipStream_t st, float2* coil, const uint8_t* mask, const float2* tw, int nc, int p, int m,
-                         int n, float scale) {
-  const long long mn = (long long)m * n, V = (long long)p * mn;
-  const dim3 grid((unsigned)(mn / col_tile(p)), nc);
+                         int n, int x0, int X, float scale) {
+  const long long mX = (long long)m * X;
+  const dim3 grid((unsigned)(mX / col_tile(p)), nc);
   switch (p) {
-#define PICS_CASE(P)                                                                                      \
-  case P:                                                                                                 \
-    hipLaunchKernelGGL(k3_col_z<P>, grid, dim3(ColCfg<P>::THREADS), 0, st, coil, mask, tw, mn, V, scale); \
+#define PICS_CASE(P)                                                                                               \
+  case P:                                                                                                          \
+    hipLaunchKernelGGL(k3_col_z<P>, grid, dim3(ColCfg<P>::THREADS), 0, st, coil, mask, tw, n, x0, X, mX, scale); \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE
@@ -411,14 +425,15 @@ hipError_t launch3_col_z(hipStream_t st, float2* coil, const uint8_t* mask, cons
 }
 
 hipError_t launch3_col_acc(hipStream_t st, const float2* S, const float2* coil, const float2* x, float2* y,
-                           const float2* tw, int nc, int p, int m, int n, float mu, float lam, float gam, int data) {
+                           const float2* tw, int nc, int p, int m, int n, float mu, float lam, float gam, int data,
+                           int x0, int X) {
   const long long V = (long long)p * m * n;
-  const dim3 grid(n / col_tile(m), p);
+  const dim3 grid(X / col_tile(m), p);
   switch (m) {
 #define PICS_CASE(M)                                                                                          \
   case M:                                                                                                     \
     hipLaunchKernelGGL(k3_col_acc<M>, grid, dim3(ColCfg<M>::THREADS), 0, st, S, coil, x, y, tw, nc, p, n, V, \
-                       mu, lam, gam, data);                                                                   \
+                       mu, lam, gam, data, x0, X);                                                            \
     break;
     PICS_FFT_SIZES(PICS_CASE)
 #undef PICS_CASE

@@ -24,7 +24,7 @@ def _declared_functions():
 
 def _defines():
     out = {}
-    for name, val in re.findall(r"^#define\s+(PICS_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", HEADER.read_text(), flags=re.M):
+    for name, val in re.findall(r"^#define\s+(PICS(?:3D)?_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", HEADER.read_text(), flags=re.M):
         out[name] = int(val)
     return out
 
@@ -79,6 +79,7 @@ def test_binding_constants_match_header():
     assert d["PICS_OPT_CONCURRENT_GROUPS"] == B.OPT_CONCURRENT_GROUPS
     assert d["PICS_OPT_COL_TILE"] == B.OPT_COL_TILE
     assert d["PICS_OPT_GRAPH_FIRST_BUDGET"] == B.OPT_GRAPH_FIRST_BUDGET
+    assert d["PICS3D_OPT_XCHUNK"] == B.OPT3_XCHUNK
     assert d["PICS_TUNE_FORCE"] == B.TUNE_FORCE
     assert d["PICS_TUNE_NO_WRITE"] == B.TUNE_NO_WRITE
 

@@ -133,3 +133,37 @@ def test_volume_operator_mask_varying_along_x(torch, B, shape):
         _say(f"  {label}: operator rel err {err:.2e}")
         assert err < 1e-5
         vol.close()
+
+
+@pytest.mark.parametrize("spec", [LARGE, gen.VolumeSpec(64, 64, 192, 3, 4.0, 8)], ids=["64x128x128x8", "64x64x192x3"])
+def test_volume_operator_every_x_chunk(torch, B, spec):
+    """The x-constant operator taken in x chunks (PICS3D_OPT_XCHUNK): every
+    admissible chunk width against the oracle, all widths bitwise equal (each
+    column's arithmetic does not depend on the chunking), invalid widths
+    refused."""
+    p, m, n = spec.p, spec.m, spec.n
+    _say(f"3D {p}x{m}x{n}x{spec.ncoils}: x chunks")
+    it = gen.make_volume_instance(spec, gen.eval_seed(8, 7))
+    assert np.all(it.mask == it.mask[:, :, :1])
+    vol, _ = B.volume_for(it)
+    x = _rand((p, m, n), 3)
+    xd = B.to_device(x.astype(np.complex64).ravel())
+    ref = ov.apply_A3(x, it.sens, it.mask.astype(np.float64), spec.mu, spec.lam, spec.gam)
+    first = None
+    for X in [c for c in range(16, n + 1, 16) if n % c == 0] + [0]:
+        vol.set_option(B.OPT3_XCHUNK, X)
+        used = vol.get_option(B.OPT3_XCHUNK)
+        assert used == (X or used) and n % used == 0
+        yd = torch.empty_like(xd)
+        vol.apply_A(xd, yd)
+        y = yd.cpu().numpy()
+        err = H.rel_err(y.reshape(p, m, n), ref)
+        _say(f"  X = {X} (in use {used}): rel err {err:.2e}")
+        assert err < 1e-5
+        if first is None:
+            first = y
+        assert np.array_equal(y, first)
+    for bad in (8, 24, n + 16, -16):
+        with pytest.raises(B.PicsError):
+            vol.set_option(B.OPT3_XCHUNK, bad)
+    vol.close()
