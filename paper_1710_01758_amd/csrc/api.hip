@@ -1370,7 +1370,7 @@ int pics_net_loss_grad(pics_net* n, int32_t batch, const int32_t* index, const f
     const NetLayer& ly = n->L.layer[l];
     const int count = ly.cout * ly.cin * 9 + ly.cout;
     NETCHK(n, launch_conv_bwd_w(n->stream, ly.cinp, ly.cin, ly.cout, n->act[l], n->gbuf[cur], ly.dil, batch, n->part));
-    NETCHK(n, launch_reduce_rows(n->stream, n->part, (int)rows, count, n->grad + ly.woff));
+    NETCHK(n, launch_reduce_rows(n->stream, n->part, (int)(rows / kWgRows), count, n->grad + ly.woff));
     if (l > 0) {
       NETCHK(n, launch_conv_bwd_data(n->stream, ly.cinp, ly.cout, n->gbuf[cur], ly.wb, n->act[l], ly.dil, batch,
                                      n->gbuf[1 - cur]));

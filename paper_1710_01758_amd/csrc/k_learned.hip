@@ -5,8 +5,9 @@
 // Activations are bf16, NHWC ([image][row][col][channel]); 3x3 convolutions
 // with circular padding run as implicit GEMMs on the 16x16x16 bf16 matrix
 // cores (FP32 accumulation): forward Y[p][o] = sum_(tap,c) X[p + off(tap)][c] W[o][c][tap],
-// backward-data dX[p][c] = sum_(tap,o) G[p - off(tap)][o] W[o][c][tap].  The
-// weight gradient is a reduction over all pixels and runs on the vector ALUs.
+// backward-data dX[p][c] = sum_(tap,o) G[p - off(tap)][o] W[o][c][tap], and the
+// weight gradient dW[o][c][tap] = sum_p G[p][o] X[p + off(tap)][c] with the
+// pixels as the inner dimension.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -195,48 +196,87 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t* __restric
   }
 }
 
-// Partial weight and bias gradients of one image row:
-// part[blk][((o * cin + c) * 9 + tap)] = sum_px x[p + off(tap)][c] g[p][o],
-// part[blk][cout * cin * 9 + o] = sum_px g[p][o]   (real input channels only).
+// Weight and bias gradients of one 3x3 layer, partial over kWgRows image rows
+// of one image (blk = b (G / kWgRows) + row group):
+//   part[blk][(o cin + c) 9 + tap] = sum_px X[px + off(tap)][c] G[px][o],
+//   part[blk][cout cin 9 + o]      = sum_px G[px][o]   (real input channels only).
+// For each tap the sum over pixels is a product with the pixels as the inner
+// dimension, run on the 16x16x16 bf16 matrix cores: A = G^T (16 output
+// channels x 16 pixels), B = X_tap (16 pixels x 16 input channels).  Per row
+// the workgroup stages G^T [o][px] and, per tap, the shifted input row
+// X_tap^T [c][px] in LDS, so that each lane's operand (4 consecutive pixels of
+// one channel) is one 8-byte load.  Wave wv takes the (o, c) tile pair
+// wv % PAIRS and the taps t with t % (4 / PAIRS) == wv / PAIRS.
 template <int CINP, int COUT>
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ x, const uint16_t* __restrict__ g,
                                                     int cin, int dil, float* __restrict__ part) {
-  constexpr int G = kNetGrid;
-  __shared__ float sx[3][G][CINP];
-  __shared__ float sg[G][COUT];
-  const int b = blockIdx.y, row = blockIdx.x;
-  for (int q = threadIdx.x; q < 3 * G * CINP; q += blockDim.x) {
-    const int r = q / (G * CINP), rem = q % (G * CINP);
-    const int ny = (row + dil * (r - 1) + 4 * G) % G;
-    sx[r][rem / CINP][rem % CINP] = bf2f(x[(((long long)b * G + ny) * G) * CINP + rem]);
-  }
-  for (int q = threadIdx.x; q < G * COUT; q += blockDim.x)
-    sg[q / COUT][q % COUT] = bf2f(g[(((long long)b * G + row) * G) * COUT + q]);
-  __syncthreads();
-  const int nw = COUT * cin * 9;
-  float* out = part + ((long long)b * G + row) * (nw + COUT);
-  for (int q = threadIdx.x; q < nw + COUT; q += blockDim.x) {
-    float acc = 0.f;
-    if (q < nw) {
-      const int o = q / (cin * 9), r = q % (cin * 9), c = r / 9, tap = r % 9;
-      const int ry = tap / 3, dx = dil * (tap % 3 - 1);
-      for (int px = 0; px < G; ++px) acc += sx[ry][(px + dx + 4 * G) % G][c] * sg[px][o];
-    } else {
-      const int o = q - nw;
-      for (int px = 0; px < G; ++px) acc += sg[px][o];
+  constexpr int G = kNetGrid, GS = G + 4;  // LDS row stride (pixels), padded against bank conflicts
+  constexpr int NO = COUT / 16, NCH = CINP / 16, PAIRS = NO * NCH, TSTEP = 4 / PAIRS;
+  static_assert(PAIRS == 1 || PAIRS == 2 || PAIRS == 4, "tile pairs must divide the four waves");
+  __shared__ __align__(16) uint16_t sgT[COUT][GS];
+  __shared__ __align__(16) uint16_t sxT[9][CINP][GS];
+  const int b = blockIdx.y, rg = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, kq = (lane >> 4) * 4;
+  const int pair = wv % PAIRS, tsel = wv / PAIRS;
+  const int o0 = (pair / NCH) * 16, c0 = (pair % NCH) * 16;
+  floatx4 acc[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) acc[tap] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float bias = 0.f;  // thread o < COUT: sum of G[px][o] over the rows
+  const uint16_t* xb = x + (long long)b * G * G * CINP;
+  for (int rr = 0; rr < kWgRows; ++rr) {
+    const int row = rg * kWgRows + rr;
+    __syncthreads();  // the previous row's products are done with the LDS rows
+    const uint16_t* gr = g + (((long long)b * G + row) * G) * COUT;
+    for (int q = threadIdx.x; q < G * COUT; q += 256) sgT[q % COUT][q / COUT] = gr[q];
+    for (int q = threadIdx.x; q < 9 * G * CINP; q += 256) {
+      const int tap = q / (G * CINP), rem = q % (G * CINP), px = rem / CINP, c = rem % CINP;
+      const int ny = (row + dil * (tap / 3 - 1) + 4 * G) % G;
+      const int nx = (px + dil * (tap % 3 - 1) + 4 * G) % G;
+      sxT[tap][c][px] = xb[((long long)ny * G + nx) * CINP + c];
     }
-    out[q] = acc;
+    __syncthreads();
+    if (threadIdx.x < COUT)
+      for (int px = 0; px < G; ++px) bias += bf2f(sgT[threadIdx.x][px]);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      if (tap % TSTEP != tsel) continue;
+#pragma unroll
+      for (int k0 = 0; k0 < G; k0 += 16) {
+        const bf16x4 av = *(const bf16x4*)&sgT[o0 + li][k0 + kq];
+        const bf16x4 bv = *(const bf16x4*)&sxT[tap][c0 + li][k0 + kq];
+        acc[tap] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[tap], 0, 0, 0);
+      }
+    }
   }
+  // D[4 (lane / 16) + i][lane % 16] = dW_tap[o0 + kq + i][c0 + li]
+  const int nw = COUT * cin * 9;
+  float* out = part + ((long long)b * (G / kWgRows) + rg) * (nw + COUT);
+  const int c = c0 + li;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    if (tap % TSTEP != tsel || c >= cin) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[((long long)(o0 + kq + i) * cin + c) * 9 + tap] = acc[tap][i];
+  }
+  if (threadIdx.x < COUT) out[nw + threadIdx.x] = bias;
 }
 
-// grad[dst + j] = sum_i part[i][j] (fixed order), j < count
+// grad[j] = sum_i part[i][j], j < count: per column four interleaved row
+// groups (rows i = grp, grp + 4, ...) summed in FP64, then added in group
+// order (a fixed order for a given row count)
 __global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int rows, int count,
                                                      float* __restrict__ grad) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int i = 0; i < rows; ++i) acc += part[(long long)i * count + j];
-    grad[j] = (float)acc;
-  }
+  __shared__ double sacc[4][64];
+  const int jl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + jl;
+  double acc = 0.0;
+  if (j < count)
+    for (int i = grp; i < rows; i += 4) acc += part[(long long)i * count + j];
+  sacc[grp][jl] = acc;
+  __syncthreads();
+  if (grp == 0 && j < count) grad[j] = (float)(((sacc[0][jl] + sacc[1][jl]) + sacc[2][jl]) + sacc[3][jl]);
 }
 
 // --------------------------------------------------------------- the head
@@ -415,7 +455,7 @@ hipError_t launch_conv_bwd_data(hipStream_t st, int cinp, int cout, const uint16
 
 hipError_t launch_conv_bwd_w(hipStream_t st, int cinp, int cin, int cout, const uint16_t* x, const uint16_t* g,
                              int dil, int batch, float* part) {
-  const dim3 grid(kNetGrid, batch);
+  const dim3 grid(kNetGrid / kWgRows, batch);
   if (cinp == 16 && cout == 32) hipLaunchKernelGGL((k_conv_bwd_w<16, 32>), grid, dim3(256), 0, st, x, g, cin, dil, part);
   else if (cinp == 32 && cout == 32)
     hipLaunchKernelGGL((k_conv_bwd_w<32, 32>), grid, dim3(256), 0, st, x, g, cin, dil, part);
@@ -426,8 +466,7 @@ hipError_t launch_conv_bwd_w(hipStream_t st, int cinp, int cin, int cout, const 
 }
 
 hipError_t launch_reduce_rows(hipStream_t st, const float* part, int rows, int count, float* grad) {
-  hipLaunchKernelGGL(k_reduce_rows, dim3(std::max(1, std::min(64, (count + 255) / 256))), dim3(256), 0, st, part, rows,
-                     count, grad);
+  hipLaunchKernelGGL(k_reduce_rows, dim3((count + 63) / 64), dim3(256), 0, st, part, rows, count, grad);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@ constexpr int kNetGrid = 64;   // frequency grid of the network
 constexpr int kNetFeat = 6;    // input feature planes
 constexpr int kNetLayers = 6;  // 3x3 layers (a 1x1 layer follows)
 constexpr float kNetFloor = 1e-3f;
+constexpr int kWgRows = 4;  // image rows per workgroup of the weight gradient (partials per image: kNetGrid / kWgRows)
 
 struct NetLayer {
   int cin, cinp, cout, dil;  // real / padded input channels, output channels, dilation
@@ -30,6 +31,7 @@ hipError_t launch_conv_fwd(hipStream_t st, int cinp, int cout, const uint16_t* x
                            const float* bias, int dil, int batch, uint16_t* y);
 hipError_t launch_conv_bwd_data(hipStream_t st, int cinp, int cout, const uint16_t* g, const uint16_t* wb,
                                 const uint16_t* xact, int dil, int batch, uint16_t* gprev);
+// part: batch * (kNetGrid / kWgRows) partial rows of cout * cin * 9 + cout
 hipError_t launch_conv_bwd_w(hipStream_t st, int cinp, int cin, int cout, const uint16_t* x, const uint16_t* g,
                              int dil, int batch, float* part);
 hipError_t launch_reduce_rows(hipStream_t st, const float* part, int rows, int count, float* grad);
