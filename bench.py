@@ -140,6 +140,7 @@ def run_apply_ragged(torch, B):
                           "coil_split": split, "apply_avg_us": round(t * 1e6, 2), "bytes_per_launch": b,
                           "achieved_GBs": round(b / t / 1e9, 1)}), flush=True)
         ctx.close()
+    copy_calibration(torch)  # for counter runs: a copy of known size
 
 
 def run_step_mode(torch, B, spec, steps):
