@@ -234,8 +234,11 @@ int pics_coil_compress(pics_ctx* ctx, const void* kspace, int32_t nvirt, void* k
  *   Default 8.
  * PICS_OPT_COIL_GROUPS: split every column tile's coil loop over this many
  *   workgroups (clamped to each group's coil count), overriding the
- *   autotuner; 1 = no split (the default before pics_autotune).  A split
- *   above 1 runs with the default column tiles.
+ *   autotuner; 1 = no split (the default before pics_autotune).  The split
+ *   applies to the size group's slice with the most coils; a slice with
+ *   fewer coils takes only as many workgroups as keep each at or below that
+ *   slice's coils per workgroup.  A split above 1 runs with the default
+ *   column tiles.
  * PICS_OPT_COL_TILE: columns per workgroup of the line-mask operator for
  *   every size group, overriding the autotuner: 0 = the default (16 up to
  *   length 320, 4 at 512, 8 at 1024) or one of the two alternatives of each

@@ -247,7 +247,7 @@ hipError_t launch_operator(pics_ctx* c, const pics_ctx::Group& g, int mode, int 
   // a coil split runs with the default tiles (the tuner never pairs the two)
   const int tile = split > 1 ? 0 : g.tile;
   return launch_col_apply(make_launch(c, g), ws_for(c, g), mode, terms, pk, tol, xin, zsrc, pold, pn, out, split,
-                          dpart, c->img_total, tile);
+                          dpart, c->img_total, tile, g.nc_max);
 }
 
 }  // namespace
@@ -1577,7 +1577,7 @@ int pics_autotune(pics_ctx* c, int32_t flags) {
       if (rc) return rc;
       auto run = [&]() {
         return launch_col_apply(make_launch(c, g), ws_for(c, g), CA_APPLY, TERM_ALL, c->pk, 0.0, c->p, nullptr,
-                                nullptr, nullptr, c->q, G, c->dpart, c->img_total, tile);
+                                nullptr, nullptr, c->q, G, c->dpart, c->img_total, tile, g.nc_max);
       };
       for (int k = 0; k < 2; ++k) HIPCHK(c, run());
       HIPCHK(c, hipEventRecord(e0, c->stream));

@@ -166,14 +166,17 @@ struct Simple {
 bool fft_size_supported(int N);
 
 // ---- FFT-path launchers (k_fft_ops.hip)
-// ngroups > 1 splits the coil loop over that many workgroups per tile
+// ngroups > 1 splits the coil loop over up to that many workgroups per tile
 // (partial data terms in dpart[group][image-packed], stride dstride elements)
-// and adds them in a second pass.
+// and adds them in a second pass.  ncmax > 0: the group's largest coil count;
+// a slice then takes only as many workgroups as keep each at or below
+// ceil(ncmax / ngroups) coils (0: every slice takes ngroups).
 // tile: the operator's column-tile width (0 = col_tile(m); else one of
 // apply_tile_alt(m, 0 / 1), with no coil split).
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            int ngroups = 1, float2* dpart = nullptr, long long dstride = 0, int tile = 0);
+                            int ngroups = 1, float2* dpart = nullptr, long long dstride = 0, int tile = 0,
+                            int ncmax = 0);
 // tile widths launch_col_apply accepts for an m x n slice
 bool apply_tile_ok(int m, int n, int tile);
 // RU_SETUP also resets the slices' PCG state (iteration limit maxit, or

@@ -23,16 +23,20 @@ namespace pics {
 //      CA_PCG    p = zs + beta p_old (beta from the rho partials), written to pn;
 //                sigma = Re(p^H A p) partial
 // PH AP_FUSED  everything in one launch
-//    AP_PART   grid.z = ngroups workgroups per column tile; group z takes coils
-//              z, z + ngroups, ... and writes its partial data term to
-//              dpart[z] (CA_PCG: group 0 also writes pn)
-//    AP_FIN    adds the partial sums in group order, then the diagonal terms
-//              and the mode's outputs (CA_PCG reads p back from pn)
+//    AP_PART   grid.z = ngroups workgroups per column tile; a slice with nc
+//              coils uses gs = min(ngroups, ceil(nc / kpg)) of them (all
+//              ngroups when kpg = 0), so that no workgroup of a batch with
+//              uneven coil counts holds more than kpg coils; group z < gs
+//              takes coils z, z + gs, ... and writes its partial data term to
+//              dpart[z] (CA_PCG: group 0 also writes pn); groups z >= gs exit
+//    AP_FIN    adds the slice's gs partial sums in group order, then the
+//              diagonal terms and the mode's outputs (CA_PCG reads p back
+//              from pn)
 // ----------------------------------------------------------------------------
 template <int M, int MODE, int PH, int TW = col_tile(M)>
 __global__ __launch_bounds__((ApplyCfg<M, TW>::THREADS), (ApplyCfg<M, TW>::MIN_BLOCKS)) void k_col_apply(
     Ws w, int terms, int pk, double tol, const float2* __restrict__ xin, const float2* __restrict__ zsrc,
-    const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, int ngroups,
+    const float2* __restrict__ pold, float2* __restrict__ pn, float2* __restrict__ out, int ngroups, int kpg,
     float2* __restrict__ dpart, long long dstride) {
   using Cfg = ApplyCfg<M, TW>;
   constexpr int NT = Cfg::NT, E = Cfg::E, T = Cfg::T, TH = Cfg::THREADS;
@@ -46,6 +50,8 @@ __global__ __launch_bounds__((ApplyCfg<M, TW>::THREADS), (ApplyCfg<M, TW>::MIN_B
   const int s = w.group[blockIdx.y];
   const SliceDev sd = w.sl[s];
   const int n = sd.n;
+  const int gs = kpg > 0 ? min(ngroups, (sd.nc + kpg - 1) / kpg) : ngroups;  // this slice's coil groups
+  if (PH == AP_PART && (int)blockIdx.z >= gs) return;
   const int j = threadIdx.x % T, t = threadIdx.x / T;
   const int j0 = xcd_tile(blockIdx.x, gridDim.x) * T;
   const int col = j0 + j;
@@ -142,15 +148,15 @@ __global__ __launch_bounds__((ApplyCfg<M, TW>::THREADS), (ApplyCfg<M, TW>::MIN_B
   }
   if (!LATE_HALO) load_halo();
   // data term sum_c conj(S_c) F^H R F (S_c p), coil maps of c + 1 in flight.
-  // AP_PART: coils c = z, z + ngroups, ... of group z = blockIdx.z, result to
+  // AP_PART: coils c = z, z + gs, ... of group z = blockIdx.z, result to
   // dpart[z]; AP_FIN: the groups' partial sums added in group order.
   float2 acc[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
   const int c0 = PH == AP_PART ? (int)blockIdx.z : 0;
-  const int cstep = PH == AP_PART ? ngroups : 1;
+  const int cstep = PH == AP_PART ? gs : 1;
   if (PH == AP_FIN) {
-    for (int gidx = 0; gidx < ngroups; ++gidx) {
+    for (int gidx = 0; gidx < gs; ++gidx) {
       const float2* __restrict__ dp = dpart + gidx * dstride + sd.img;
 #pragma unroll
       for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], dp[(t + NT * e) * n + col]);
@@ -761,14 +767,14 @@ __global__ __launch_bounds__(ColCfg<M>::THREADS) void k_col_coil_energy(Ws w, co
 template <int M, int PH, int TW = col_tile(M)>
 void launch_col_apply_phase(dim3 grid, const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            int ngroups, float2* dpart, long long dstride) {
+                            int ngroups, int kpg, float2* dpart, long long dstride) {
   const dim3 block(ApplyCfg<M, TW>::THREADS);
   if (mode == CA_PCG)
     hipLaunchKernelGGL((k_col_apply<M, CA_PCG, PH, TW>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc,
-                       pold, pn, out, ngroups, dpart, dstride);
+                       pold, pn, out, ngroups, kpg, dpart, dstride);
   else
     hipLaunchKernelGGL((k_col_apply<M, CA_APPLY, PH, TW>), grid, block, 0, L.stream, w, terms, pk, tol, xin, zsrc,
-                       pold, pn, out, ngroups, dpart, dstride);
+                       pold, pn, out, ngroups, kpg, dpart, dstride);
 }
 
 bool apply_tile_ok(int m, int n, int tile) {
@@ -779,8 +785,10 @@ bool apply_tile_ok(int m, int n, int tile) {
 
 hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, int pk, double tol,
                             const float2* xin, const float2* zsrc, const float2* pold, float2* pn, float2* out,
-                            int ngroups, float2* dpart, long long dstride, int tile) {
+                            int ngroups, float2* dpart, long long dstride, int tile, int ncmax) {
   const int split = (ngroups > 1 && (terms & TERM_DATA)) ? ngroups : 1;
+  // coils per partial workgroup: the largest slice's split (0: every slice split ngroups ways)
+  const int kpg = split > 1 && ncmax > 0 ? (ncmax + split - 1) / split : 0;
   if (split > 1 && !dpart) return hipErrorInvalidValue;
   if (tile == 0) tile = col_tile(L.m);
   // a coil split runs with the default tiles only
@@ -791,19 +799,19 @@ hipError_t launch_col_apply(const Launch& L, const Ws& w, int mode, int terms, i
   case M:                                                                                                       \
     if (tile == apply_tile_alt(M, 0)) {                                                                         \
       launch_col_apply_phase<M, AP_FUSED, apply_tile_alt(M, 0)>(grid, L, w, mode, terms, pk, tol, xin, zsrc,     \
-                                                               pold, pn, out, 1, dpart, dstride);              \
+                                                               pold, pn, out, 1, 0, dpart, dstride);           \
     } else if (tile == apply_tile_alt(M, 1)) {                                                                  \
       launch_col_apply_phase<M, AP_FUSED, apply_tile_alt(M, 1)>(grid, L, w, mode, terms, pk, tol, xin, zsrc,     \
-                                                               pold, pn, out, 1, dpart, dstride);              \
+                                                               pold, pn, out, 1, 0, dpart, dstride);           \
     } else if (split == 1) {                                                                                    \
-      launch_col_apply_phase<M, AP_FUSED>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, 1, dpart, \
-                                          dstride);                                                            \
+      launch_col_apply_phase<M, AP_FUSED>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, 1, 0,      \
+                                          dpart, dstride);                                                     \
     } else {                                                                                                    \
       launch_col_apply_phase<M, AP_PART>(dim3(grid.x, grid.y, split), L, w, mode, terms, pk, tol, xin, zsrc,    \
-                                         pold, pn, out, split, dpart, dstride);                                \
+                                         pold, pn, out, split, kpg, dpart, dstride);                           \
       const hipError_t e = hipGetLastError();                                                                   \
       if (e != hipSuccess) return e;                                                                            \
-      launch_col_apply_phase<M, AP_FIN>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, split,      \
+      launch_col_apply_phase<M, AP_FIN>(grid, L, w, mode, terms, pk, tol, xin, zsrc, pold, pn, out, split, kpg, \
                                         dpart, dstride);                                                       \
     }                                                                                                           \
     break;
