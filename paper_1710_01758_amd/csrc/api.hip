@@ -1475,9 +1475,12 @@ std::string device_tag() {
   return buf;
 }
 
+// v2: the split applies to the group's slice with the most coils, the
+// others take workgroups in proportion (entries of the uniform split are
+// not reused)
 std::string group_key(const pics_ctx::Group& g) {
   char buf[160];
-  snprintf(buf, sizeof buf, "%s m%d n%d nc%d b%d", device_tag().c_str(), g.m, g.n, g.nc_max, (int)g.idx.size());
+  snprintf(buf, sizeof buf, "v2 %s m%d n%d nc%d b%d", device_tag().c_str(), g.m, g.n, g.nc_max, (int)g.idx.size());
   return buf;
 }
 
