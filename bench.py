@@ -124,10 +124,10 @@ def run_apply_ragged(torch, B):
     """The ragged 64-slice batch's operator: the whole batch (size groups on
     side streams), then each size group alone in its own context (one JSON
     line each)."""
-    specs = gen.cfg4_specs()
+    specs = gen.ragged_specs()
     insts = [gen.make_instance(sp, gen.eval_seed(4, i)) for i, sp in enumerate(specs)]
     groups = [("all", insts)]
-    for shape in gen.CFG4_SHAPES:
+    for shape in gen.RAGGED_SHAPES:
         groups.append((f"{shape[0]}x{shape[1]}", [it for it in insts if (it.spec.m, it.spec.n) == shape]))
     for label, gi in groups:
         ctx, _ = B.context_for(gi)
@@ -581,7 +581,7 @@ def learned_section(torch, B, steps):
     tr1 = LD.dataset_loss(net, train)
     floor = superoptimal_loss(held)
     tfloor = superoptimal_loss(train)
-    inst = gen.make_instance(gen.CFG5, gen.eval_seed(5))
+    inst = gen.make_instance(gen.LEARNED_SLICE, gen.eval_seed(5))
     sb = LD.evaluate_on(inst, net, n_outer=20)
     pcg = LD.pcg_first_solve(inst, net, curve=3)
     inst_s = gen.make_instance(gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1e3),
@@ -905,7 +905,7 @@ def main():
     if not a.no_extra:
         log("bench: 512x512x32 slice")
         out["slice_512x512x32"] = workload_section(
-            torch, B, [gen.make_instance(gen.CFG3, gen.eval_seed(3))],
+            torch, B, [gen.make_instance(gen.SLICE_512, gen.eval_seed(3))],
             "512x512, 32 coils, variable-density lines R=6 (32 centre), TV + db4 x4")
         log("bench: 1024x1024x12 slice")
         out["slice_1024x1024x12"] = workload_section(
@@ -913,7 +913,7 @@ def main():
                                          gen.eval_seed(7))],
             "1024x1024, 12 coils, random lines R=4 (64 centre), TV + db4 x4 (the paper's largest size)")
         log("bench: ragged batch of 64 slices")
-        specs = gen.cfg4_specs()
+        specs = gen.ragged_specs()
         out["ragged_batch_64"] = workload_section(
             torch, B, [gen.make_instance(sp, gen.eval_seed(4, i)) for i, sp in enumerate(specs)],
             "64 slices {128^2, 192^2, 256x224, 320^2}, 8-32 coils, R in {3,4,6}, TV + db4 x3")

@@ -64,21 +64,25 @@ class SliceSpec:
 PARAM_SETS = {1: (1e-3, 4e-3, 1e-3), 2: (1e-2, 4e-3, 1e-3), 3: (1e-3, 4e-3, 4e-3)}
 
 
-CFG1 = SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1)
-CFG2 = SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3)
-CFG3 = SliceSpec(512, 512, 32, 6.0, 32, vd=True, wavelet="db4", levels=4)
-CFG5 = CFG2  # learned correction is evaluated on the 256^2 x 12 slice
+SLICE_64 = SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1)
+SLICE_256 = SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3)
+SLICE_512 = SliceSpec(512, 512, 32, 6.0, 32, vd=True, wavelet="db4", levels=4)
+LEARNED_SLICE = SLICE_256  # learned correction is evaluated on the 256^2 x 12 slice
 
-CFG4_SHAPES = ((128, 128), (192, 192), (256, 224), (320, 320))
-CFG4_ACCELS = (3.0, 4.0, 6.0)
+RAGGED_SHAPES = ((128, 128), (192, 192), (256, 224), (320, 320))
+RAGGED_ACCELS = (3.0, 4.0, 6.0)
 
 EVAL_SEED_BASE = 17_100_000
 TRAIN_SEED_BASE = 20_000
 HELDOUT_SEED_BASE = 30_000
 
 
-def eval_seed(cfg: int, slice_index: int = 0) -> int:
-    return EVAL_SEED_BASE + 1000 * cfg + slice_index
+def eval_seed(family: int, slice_index: int = 0) -> int:
+    """Seed of evaluation instance `slice_index` of a seed family (families
+    keep the instances of different workloads and tests apart: 1 the 64²
+    slice, 2 the 256² slice, 3 the 512² slice, 4 the ragged batch, 5 the
+    learned-correction slice, others for individual tests)."""
+    return EVAL_SEED_BASE + 1000 * family + slice_index
 
 
 # ----------------------------------------------------------------------------
@@ -232,17 +236,17 @@ def make_instance(spec: SliceSpec, seed: int) -> Instance:
     return Instance(spec, seed, x, S, mask, y)
 
 
-def cfg4_specs(seed: int = None, nslices: int = 64) -> List[SliceSpec]:
-    """The ragged batch: per slice a size from CFG4_SHAPES, 8..32 coils and
+def ragged_specs(seed: int = None, nslices: int = 64) -> List[SliceSpec]:
+    """The ragged batch: per slice a size from RAGGED_SHAPES, 8..32 coils and
     R in {3, 4, 6}; centre = 2 round(6 m / 128); db4 with 3 levels."""
     if seed is None:
         seed = eval_seed(4, 999)
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for _ in range(nslices):
-        m, n = CFG4_SHAPES[int(rng.integers(0, len(CFG4_SHAPES)))]
+        m, n = RAGGED_SHAPES[int(rng.integers(0, len(RAGGED_SHAPES)))]
         nc = int(rng.integers(8, 33))
-        accel = float(CFG4_ACCELS[int(rng.integers(0, len(CFG4_ACCELS)))])
+        accel = float(RAGGED_ACCELS[int(rng.integers(0, len(RAGGED_ACCELS)))])
         out.append(SliceSpec(m, n, nc, accel, 2 * int(round(6 * m / 128)), wavelet="db4", levels=3))
     return out
 

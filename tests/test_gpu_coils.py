@@ -60,7 +60,7 @@ def _split(flat, insts, nvirt):
 
 def test_eigenvalues_and_compressed_operator_match_oracle(torch, B):
     _say("coil compression: eigenvalues, operator, spectrum")
-    insts = [gen.make_instance(gen.CFG2, gen.eval_seed(2)),
+    insts = [gen.make_instance(gen.SLICE_256, gen.eval_seed(2)),
              gen.make_instance(gen.SliceSpec(128, 128, 9, 3.0, 12, mask_kind="2d", wavelet="db4", levels=2), 31)]
     nvirt = 6
     ctx, cv, kout, sout, eig = _compressed(torch, B, insts, nvirt)
@@ -95,7 +95,7 @@ def test_eigenvalues_and_compressed_operator_match_oracle(torch, B):
 
 def test_full_rank_compression_reproduces_the_problem(torch, B):
     _say("coil compression: all coils kept")
-    insts = [gen.make_instance(gen.CFG1, gen.eval_seed(1))]
+    insts = [gen.make_instance(gen.SLICE_64, gen.eval_seed(1))]
     nc = insts[0].spec.ncoils
     ctx, cv, kout, sout, eig = _compressed(torch, B, insts, nc)
     x = B.to_device(B.pack_images([gen.random_image(1200, 64, 64)]))

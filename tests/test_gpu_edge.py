@@ -44,7 +44,7 @@ def _host(t):
 
 def test_zero_rhs_gives_zero_solution_without_iterations(torch, B):
     _say("edge: zero rhs")
-    it = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    it = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
     ctx, _ = B.context_for([it])
     ctx.build_preconditioner("circulant")
     b = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
@@ -56,7 +56,7 @@ def test_zero_rhs_gives_zero_solution_without_iterations(torch, B):
 
 def test_iteration_cap_is_a_warning(torch, B):
     _say("edge: maxit")
-    it = gen.make_instance(gen.CFG2, gen.eval_seed(2))
+    it = gen.make_instance(gen.SLICE_256, gen.eval_seed(2))
     s = it.spec
     ctx, _ = B.context_for([it])
     ctx.build_preconditioner("none")
@@ -107,7 +107,7 @@ def test_empty_mask_with_gamma_is_exactly_circulant(torch, B):
 
 def test_operator_without_terms_and_buffer_checks(torch, B):
     _say("edge: no terms, aliasing")
-    it = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    it = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
     ctx, _ = B.context_for([it])
     x = B.to_device(gen.random_image(7, 64, 64).astype(np.complex64).ravel())
     y = torch.full_like(x, 3.0)
@@ -124,7 +124,7 @@ def test_operator_without_terms_and_buffer_checks(torch, B):
 
 def test_zero_outer_iterations_return_the_sum_of_squares_start(torch, B):
     _say("edge: n_outer 0 and 1")
-    it = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    it = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
     ctx, ksp = B.context_for([it])
     ctx.build_preconditioner("circulant")
     x = torch.zeros(ctx.image_elems, dtype=torch.complex64, device="cuda")
@@ -171,7 +171,7 @@ def test_nonfinite_rhs_ends_only_its_slice(torch, B):
     PICS_ERR_NONFINITE, and the other slice of the batch converges exactly as
     it does alone."""
     _say("edge: NaN in one slice's rhs")
-    its = [gen.make_instance(gen.CFG1, gen.eval_seed(1, i)) for i in range(2)]
+    its = [gen.make_instance(gen.SLICE_64, gen.eval_seed(1, i)) for i in range(2)]
     ctx, _ = B.context_for(its)
     ctx.build_preconditioner("circulant")
     bh = np.concatenate([gen.random_image(40 + i, 64, 64).ravel() for i in range(2)]).astype(np.complex64)

@@ -79,9 +79,9 @@ def _sb_errors(torch, B, ctx, ksp, insts, n_outer):
 
 
 def _ragged(scale):
-    specs = gen.cfg4_specs(nslices=64)
+    specs = gen.ragged_specs(nslices=64)
     out = []
-    for shape in gen.CFG4_SHAPES:
+    for shape in gen.RAGGED_SHAPES:
         out += [(i, s) for i, s in enumerate(specs) if (s.m, s.n) == shape][:2]
     return [gen.make_instance(gen.SliceSpec(s.m, s.n, s.ncoils, s.accel, s.centre, wavelet="db4", levels=3,
                                             data_scale=scale), gen.eval_seed(4, i)) for i, s in out]

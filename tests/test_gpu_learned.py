@@ -130,7 +130,7 @@ def test_forward_loss_and_gradient_match_oracle(torch, B, small_data):
 
 def test_correction_upsampling_and_learned_pcg(torch, B, LD):
     _say("learned: correction + PCG")
-    inst = gen.make_instance(gen.CFG2, gen.eval_seed(5))
+    inst = gen.make_instance(gen.SLICE_256, gen.eval_seed(5))
     s = inst.spec
     ctx, _ = B.context_for([inst])
     khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
@@ -161,7 +161,7 @@ def test_correction_upsampling_and_learned_pcg(torch, B, LD):
 
 def test_learned_fallback_on_bad_correction(torch, B):
     _say("learned: fallback")
-    inst = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    inst = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
     ctx, _ = B.context_for([inst])
     bad = torch.full((ctx.image_elems,), -1.0, dtype=torch.float32, device="cuda")
     rc = ctx.build_preconditioner("learned", correction=bad)

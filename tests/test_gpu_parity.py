@@ -87,26 +87,26 @@ def _check_apply(torch, B, insts, tol=1e-5):
             assert H.rel_err(g, ref) < tol, (s.m, s.n, terms, H.rel_err(g, ref))
 
 
-def test_apply_A_cfg1(torch, B):
-    _say("apply_A cfg1")
-    _check_apply(torch, B, [_inst(gen.CFG1, gen.eval_seed(1))])
+def test_apply_A_64x64x4(torch, B):
+    _say("apply_A 64x64x4")
+    _check_apply(torch, B, [_inst(gen.SLICE_64, gen.eval_seed(1))])
 
 
-def test_apply_A_cfg2(torch, B):
-    _say("apply_A cfg2")
-    _check_apply(torch, B, [_inst(gen.CFG2, gen.eval_seed(2))])
+def test_apply_A_256x256x12(torch, B):
+    _say("apply_A 256x256x12")
+    _check_apply(torch, B, [_inst(gen.SLICE_256, gen.eval_seed(2))])
 
 
 def test_apply_A_ragged_batch(torch, B):
     _say("apply_A ragged batch")
-    specs = gen.cfg4_specs(nslices=6)
+    specs = gen.ragged_specs(nslices=6)
     insts = [_inst(s, 1000 + i) for i, s in enumerate(specs)]
     _check_apply(torch, B, insts)
 
 
-def test_apply_A_cfg3_512x512x32(torch, B):
-    _say("apply_A cfg3")
-    _check_apply(torch, B, [_inst(gen.CFG3, gen.eval_seed(3))])
+def test_apply_A_512x512x32(torch, B):
+    _say("apply_A 512x512x32")
+    _check_apply(torch, B, [_inst(gen.SLICE_512, gen.eval_seed(3))])
 
 
 def _check_k(torch, B, insts):
@@ -123,16 +123,16 @@ def _check_k(torch, B, insts):
 
 
 def test_circulant_k_matches_oracle(torch, B):
-    _say("k cfg1/cfg2/ragged")
-    _check_k(torch, B, [_inst(gen.CFG1, gen.eval_seed(1))])
-    _check_k(torch, B, [_inst(gen.CFG2, gen.eval_seed(2))])
-    specs = gen.cfg4_specs(nslices=5)
+    _say("k 64x64x4, 256x256x12, ragged")
+    _check_k(torch, B, [_inst(gen.SLICE_64, gen.eval_seed(1))])
+    _check_k(torch, B, [_inst(gen.SLICE_256, gen.eval_seed(2))])
+    specs = gen.ragged_specs(nslices=5)
     _check_k(torch, B, [_inst(s, 2000 + i) for i, s in enumerate(specs)])
 
 
 def test_apply_minv_matches_oracle(torch, B):
     _say("apply_Minv")
-    insts = [_inst(gen.CFG2, gen.eval_seed(2)), _inst(gen.CFG1, gen.eval_seed(1))]
+    insts = [_inst(gen.SLICE_256, gen.eval_seed(2)), _inst(gen.SLICE_64, gen.eval_seed(1))]
     ctx, _ = _ctx(B, insts)
     ctx.build_preconditioner("circulant")
     rs = [gen.random_image(300 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
@@ -171,11 +171,11 @@ def _rhs(it):
 
 
 @pytest.mark.parametrize("precond", ["circulant", "none", "jacobi"])
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_pcg_iteration_locked_and_free_running(torch, B, cfg, precond):
-    _say(f"pcg cfg{cfg} {precond}")
-    spec = gen.CFG1 if cfg == 1 else gen.CFG2
-    it = _inst(spec, gen.eval_seed(cfg))
+@pytest.mark.parametrize("size", [64, 256])
+def test_pcg_iteration_locked_and_free_running(torch, B, size, precond):
+    _say(f"pcg {size}x{size} {precond}")
+    spec = gen.SLICE_64 if size == 64 else gen.SLICE_256
+    it = _inst(spec, gen.eval_seed(1 if size == 64 else 2))
     s = spec
     r2d = it.mask2d.astype(np.float64)
     A = lambda v: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
@@ -203,14 +203,14 @@ def test_pcg_iteration_locked_and_free_running(torch, B, cfg, precond):
 
 
 @pytest.mark.parametrize("groups", [1, 4])
-def test_pcg_locked_cfg3_512x512x32(torch, B, groups):
+def test_pcg_locked_512x512x32(torch, B, groups):
     """The 512^2 x 32 slice (variable-density lines, R = 6): three circulant
     PCG iterations (two reach 1e-3; the third runs past it), locked on both
     sides, with the fused operator and with its coil loop split over 4
     workgroups per column tile (the split the autotuner picks for one such
     slice).  Covers the length-512 transforms of every PCG pass."""
-    _say(f"pcg cfg3 circulant, coil groups {groups}")
-    it = _inst(gen.CFG3, gen.eval_seed(3))
+    _say(f"pcg 512x512x32 circulant, coil groups {groups}")
+    it = _inst(gen.SLICE_512, gen.eval_seed(3))
     s = it.spec
     r2d = it.mask2d.astype(np.float64)
     A = lambda v: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
@@ -229,10 +229,10 @@ def test_pcg_locked_cfg3_512x512x32(torch, B, groups):
     assert err < 1e-4, err
 
 
-def test_pcg_locked_cfg2_longer_run(torch, B):
+def test_pcg_locked_256x256x12_longer_run(torch, B):
     """Eight iterations of unpreconditioned CG at 256^2 x 12 stay within 1e-4."""
-    _say("pcg cfg2 none locked 8")
-    it = _inst(gen.CFG2, gen.eval_seed(2))
+    _say("pcg 256x256x12 none locked 8")
+    it = _inst(gen.SLICE_256, gen.eval_seed(2))
     s = it.spec
     r2d = it.mask2d.astype(np.float64)
     A = lambda v: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
@@ -247,7 +247,7 @@ def test_pcg_locked_cfg2_longer_run(torch, B):
 
 def test_pcg_batched_equals_per_slice(torch, B):
     _say("pcg batched == per slice")
-    specs = gen.cfg4_specs(nslices=4)
+    specs = gen.ragged_specs(nslices=4)
     insts = [_inst(sp, 4000 + i) for i, sp in enumerate(specs)]
     bs = [_rhs(it) for it in insts]
     ctx, _ = _ctx(B, insts)
@@ -269,7 +269,7 @@ def test_pcg_batched_equals_per_slice(torch, B):
 
 def test_pcg_deterministic(torch, B):
     _say("pcg determinism")
-    it = _inst(gen.CFG2, gen.eval_seed(2))
+    it = _inst(gen.SLICE_256, gen.eval_seed(2))
     ctx, _ = _ctx(B, [it])
     ctx.build_preconditioner("none")
     bd = B.to_device(_rhs(it).astype(np.complex64).ravel())
@@ -282,8 +282,8 @@ def test_pcg_deterministic(torch, B):
 
 
 @pytest.mark.parametrize("scale", [1.0, 1e3])
-def test_split_bregman_cfg1_locked(torch, B, scale):
-    _say(f"sb cfg1 scale {scale}")
+def test_split_bregman_64x64x4_locked(torch, B, scale):
+    _say(f"sb 64x64x4 scale {scale}")
     spec = gen.SliceSpec(64, 64, 4, 4.0, 12, wavelet="haar", levels=1, data_scale=scale)
     it = _inst(spec, gen.eval_seed(1))
     ref = osb.split_bregman(it.kspace, it.sens, it.mask, spec.mu, spec.lam, spec.gam, "haar", 1, n_outer=20,
@@ -295,7 +295,7 @@ def test_split_bregman_cfg1_locked(torch, B, scale):
     iters, rc = ctx.split_bregman_recon(ksp, xd, n_outer=20, lock=lock)
     assert np.array_equal(iters[:, 0], lock[:, 0])
     err = H.rel_err(_host(xd).reshape(spec.m, spec.n), ref.x)
-    _say(f"  sb cfg1 scale {scale}: rel err vs oracle {err:.3e}, iters {ref.pcg_iters}")
+    _say(f"  sb 64x64x4 scale {scale}: rel err vs oracle {err:.3e}, iters {ref.pcg_iters}")
     assert err < 1e-4, err
     # free-running counts stay within one of the oracle's per solve
     xd.zero_()
@@ -303,8 +303,8 @@ def test_split_bregman_cfg1_locked(torch, B, scale):
     assert np.all(np.abs(free[:, 0] - lock[:, 0]) <= 1)
 
 
-def test_split_bregman_cfg2_locked(torch, B):
-    _say("sb cfg2 scale 1e3")
+def test_split_bregman_256x256x12_locked(torch, B):
+    _say("sb 256x256x12 scale 1e3")
     spec = gen.SliceSpec(256, 256, 12, 4.0, 24, wavelet="db4", levels=3, data_scale=1e3)
     it = _inst(spec, gen.eval_seed(2))
     ref = osb.split_bregman(it.kspace, it.sens, it.mask, spec.mu, spec.lam, spec.gam, "db4", 3, n_outer=6,
@@ -315,7 +315,7 @@ def test_split_bregman_cfg2_locked(torch, B):
     lock = np.array(ref.pcg_iters, np.int32).reshape(6, 1)
     ctx.split_bregman_recon(ksp, xd, n_outer=6, lock=lock)
     err = H.rel_err(_host(xd).reshape(spec.m, spec.n), ref.x)
-    _say(f"  sb cfg2: rel err vs oracle {err:.3e}")
+    _say(f"  sb 256x256x12: rel err vs oracle {err:.3e}")
     assert err < 1e-4, err
 
 
@@ -335,7 +335,7 @@ def test_split_bregman_graph_equals_host_polled(torch, B, scale):
     synchronisations in between, and a budget too small for some solves
     falls back to the host-polled path with the same result."""
     _say(f"sb graph vs polled, scale {scale}")
-    specs = gen.cfg4_specs(nslices=3)
+    specs = gen.ragged_specs(nslices=3)
     specs = [gen.SliceSpec(s.m, s.n, s.ncoils, s.accel, s.centre, wavelet="db4", levels=3, data_scale=scale)
              for s in specs]
     insts = [_inst(sp, 5000 + i) for i, sp in enumerate(specs)]
@@ -375,8 +375,8 @@ def test_apply_A_coil_split_matches_oracle(torch, B, groups):
     """Splitting each column tile's coil loop over several workgroups (5 does
     not divide 12 coils) keeps apply_A within tolerance of the oracle."""
     _say(f"apply_A coil split {groups}")
-    insts = [_inst(gen.CFG2, gen.eval_seed(2))]
-    specs = gen.cfg4_specs(nslices=4)
+    insts = [_inst(gen.SLICE_256, gen.eval_seed(2))]
+    specs = gen.ragged_specs(nslices=4)
     insts += [_inst(sp, 1200 + i) for i, sp in enumerate(specs)]
     ctx, _ = _ctx(B, insts)
     ctx.set_option(B.OPT_COIL_GROUPS, groups)
@@ -399,7 +399,7 @@ def test_apply_A_coil_split_matches_oracle(torch, B, groups):
 
 def test_pcg_coil_split_locked_and_deterministic(torch, B):
     _say("pcg coil split 3")
-    it = _inst(gen.CFG2, gen.eval_seed(2))
+    it = _inst(gen.SLICE_256, gen.eval_seed(2))
     s = it.spec
     r2d = it.mask2d.astype(np.float64)
     A = lambda v: ops.apply_A(v, it.sens, r2d, s.mu, s.lam, s.gam)
@@ -423,7 +423,7 @@ def test_split_bregman_coil_split_graph(torch, B):
     """Split Bregman with a coil split: graph-replayed equals host-polled bit
     for bit, and the unsplit run locked to the same PCG counts agrees."""
     _say("sb coil split graph")
-    insts = [_inst(gen.CFG2, gen.eval_seed(2 + 100 * i)) for i in range(2)]
+    insts = [_inst(gen.SLICE_256, gen.eval_seed(2 + 100 * i)) for i in range(2)]
 
     def run(groups, budget, lock=None):
         ctx, ksp = _ctx(B, insts)
@@ -446,7 +446,7 @@ def test_split_bregman_coil_split_graph(torch, B):
 def test_autotune_picks_a_valid_split(torch, B, tmp_path, monkeypatch):
     _say("autotune")
     monkeypatch.setenv("PICS_TUNE_CACHE", str(tmp_path / "tune.txt"))
-    specs = gen.cfg4_specs(nslices=6)
+    specs = gen.ragged_specs(nslices=6)
     insts = [_inst(sp, 1300 + i) for i, sp in enumerate(specs)]
     ctx, _ = _ctx(B, insts)
     choice = ctx.autotune()
@@ -472,7 +472,7 @@ def test_concurrent_size_groups_equal_serial(torch, B):
     running the groups one after the other (apply_A, M^-1, FFT, Split Bregman
     with graph replay)."""
     _say("concurrent size groups == serial")
-    specs = gen.cfg4_specs(nslices=8)
+    specs = gen.ragged_specs(nslices=8)
     insts = [_inst(sp, 6000 + i) for i, sp in enumerate(specs)]
     assert len({(s.m, s.n) for s in specs}) > 1
     outs = []

@@ -43,9 +43,9 @@ def B():
 def _ragged_specs(per_shape=2, scale=1.0):
     """The first `per_shape` slices of each size of the 64-slice ragged batch
     (its seeded coil counts and accelerations), so that every size appears."""
-    specs = gen.cfg4_specs(nslices=64)
+    specs = gen.ragged_specs(nslices=64)
     picked = []
-    for shape in gen.CFG4_SHAPES:
+    for shape in gen.RAGGED_SHAPES:
         same = [(i, s) for i, s in enumerate(specs) if (s.m, s.n) == shape][:per_shape]
         picked += same
     out = []
@@ -65,7 +65,7 @@ def _rhs(it):
 
 def test_ragged_batch_covers_every_size_coil_range_and_acceleration():
     specs = [s for _, s in _ragged_specs()]
-    assert {(s.m, s.n) for s in specs} == set(gen.CFG4_SHAPES)
+    assert {(s.m, s.n) for s in specs} == set(gen.RAGGED_SHAPES)
     assert min(s.ncoils for s in specs) >= 8 and max(s.ncoils for s in specs) <= 32
     assert len({s.accel for s in specs}) >= 2
 

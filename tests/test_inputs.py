@@ -12,16 +12,16 @@ def _h(a):
 
 
 def test_seeded_determinism():
-    a = gen.make_instance(gen.CFG1, gen.eval_seed(1))
-    b = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    a = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
+    b = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
     for f in ("x_true", "sens", "mask", "kspace"):
         assert _h(getattr(a, f)) == _h(getattr(b, f))
-    c = gen.make_instance(gen.CFG1, gen.eval_seed(1, 1))
+    c = gen.make_instance(gen.SLICE_64, gen.eval_seed(1, 1))
     assert _h(a.kspace) != _h(c.kspace)
 
 
 def test_coil_normalisation():
-    inst = gen.make_instance(gen.CFG1, 123)
+    inst = gen.make_instance(gen.SLICE_64, 123)
     s = np.sum(np.abs(inst.sens) ** 2, axis=0)
     assert np.allclose(s, 1.0, atol=1e-12)
 
@@ -52,12 +52,12 @@ def test_kspace_zero_filled_and_noise_level():
     assert 0.8e-6 < var < 1.2e-6
 
 
-def test_cfg4_batch_recipe():
-    specs = gen.cfg4_specs()
+def test_ragged_batch_recipe():
+    specs = gen.ragged_specs()
     assert len(specs) == 64
-    assert {(s.m, s.n) for s in specs} <= set(gen.CFG4_SHAPES)
+    assert {(s.m, s.n) for s in specs} <= set(gen.RAGGED_SHAPES)
     assert all(8 <= s.ncoils <= 32 for s in specs)
-    assert {s.accel for s in specs} <= set(gen.CFG4_ACCELS)
+    assert {s.accel for s in specs} <= set(gen.RAGGED_ACCELS)
     assert all(s.centre == 2 * round(6 * s.m / 128) for s in specs)
 
 

@@ -109,7 +109,7 @@ def test_adam_first_step_is_signed_learning_rate():
 
 
 def test_features_ranges():
-    inst = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+    inst = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
     s = inst.spec
     k = pre.circulant_k(inst.sens, inst.mask2d.astype(float), s.mu, s.lam, s.gam)
     f = L.features(inst.mask2d, inst.sens, k, s.mu, s.lam, s.gam)

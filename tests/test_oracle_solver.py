@@ -80,8 +80,8 @@ def test_cg_iteration_bound():
     assert res.converged and res.iters <= bound
 
 
-def test_circulant_reduces_iterations_on_cfg1():
-    inst = gen.make_instance(gen.CFG1, gen.eval_seed(1))
+def test_circulant_reduces_iterations_on_64x64x4():
+    inst = gen.make_instance(gen.SLICE_64, gen.eval_seed(1))
     s = inst.spec
     r2d = inst.mask2d.astype(np.float64)
     A = lambda v: ops.apply_A(v, inst.sens, r2d, s.mu, s.lam, s.gam)
@@ -161,7 +161,7 @@ def test_sb_kspace_form_equals_image_domain_form():
     assert H.rel_err(b.x, a.x) < 1e-10
 
 
-def test_sb_cfg1_scaled_reduces_error_and_iterations():
+def test_sb_64x64x4_scaled_reduces_error_and_iterations():
     """With data_scale 1e3 the shrink is active; the circulant preconditioner
     needs fewer PCG iterations than none and the reconstruction approaches
     the phantom."""
