@@ -99,13 +99,17 @@ def test_apply_minv_every_transform_length(torch, B, shapes):
     ctx.close()
 
 
-def test_ragged_batch_pcg_against_oracle(torch, B):
+@pytest.mark.parametrize("split", [1, 4])
+def test_ragged_batch_pcg_against_oracle(torch, B, split):
     """Circulant PCG on A x = mu E^H y for eight ragged slices at once:
     iteration-locked to each slice's oracle count within 1e-4; free-running
-    counts within one of the oracle's."""
+    counts within one of the oracle's.  With a coil split the operator runs
+    its partial and finishing passes, each slice taking as many partial
+    workgroups as its coil count needs (uneven across the batch)."""
     specs = _ragged_specs()
     insts = _instances(specs)
-    _say("ragged pcg: " + ", ".join(f"{it.spec.m}x{it.spec.n}x{it.spec.ncoils} R{it.spec.accel:g}" for it in insts))
+    _say(f"ragged pcg, coil split {split}: " +
+         ", ".join(f"{it.spec.m}x{it.spec.n}x{it.spec.ncoils} R{it.spec.accel:g}" for it in insts))
     bs = [_rhs(it) for it in insts]
     refs = []
     for it, b in zip(insts, bs):
@@ -115,6 +119,8 @@ def test_ragged_batch_pcg_against_oracle(torch, B):
         minv = osb.make_minv("circulant", it.sens, r2d, s.mu, s.lam, s.gam)
         refs.append((opcg.pcg(A, b, np.zeros_like(b), minv, 1e-3, 1000), A))
     ctx, _ = B.context_for(insts)
+    if split > 1:
+        ctx.set_option(B.OPT_COIL_GROUPS, split)
     ctx.build_preconditioner("circulant")
     bd = B.to_device(B.pack_images(bs))
     xd = torch.zeros_like(bd)
