@@ -928,6 +928,10 @@ def main():
         out["param_sets_256x256x12"] = param_sets_section(torch, B)
     if not a.no_learned:
         out["learned"] = learned_section(torch, B, a.train_steps)
+        # the metric's second half in one place: PCG iterations from 0 to 1e-3
+        # on the 256^2 x 12 slice, per preconditioner
+        pz = out["learned"]["slice_256x256x12"]["pcg_from_zero"]
+        out["pcg_iters_to_1e-3_256x256x12"] = {k: v["iters_to_1e-3"] for k, v in pz.items()}
     if not a.no_cpu_baseline:
         log("bench: cpu baseline (oracle), one core")
         one = cpu_baseline(insts[0])
