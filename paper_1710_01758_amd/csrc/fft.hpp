@@ -321,14 +321,11 @@ constexpr int kSupportedSizes[] = {64, 128, 192, 224, 256, 320, 512, 1024};
 // LDS layouts: Lay::addr(idx, seq) gives the slot of element idx of sequence
 // seq.  Column tiles keep T sequences side by side (row-major like global
 // memory); row tiles keep each sequence contiguous with one pad slot per 16.
-// Tiles narrower than 16 columns pad PICS_COLPAD slots per 16 elements (a
-// build option) to spread the first exchange's stores over the banks.
-#ifndef PICS_COLPAD
-#define PICS_COLPAD 4
-#endif
+// Tiles narrower than 16 columns pad 4 slots per 16 elements to spread the
+// first exchange's stores over the banks.
 template <int T>
 struct ColLay {
-  static constexpr int pad = T < 16 ? PICS_COLPAD : 0;
+  static constexpr int pad = T < 16 ? 4 : 0;
   template <int M>
   static constexpr int size = M * T + ((M + 15) / 16) * pad;
   static __device__ __forceinline__ int addr(int idx, int seq) { return idx * T + seq + (idx >> 4) * pad; }

@@ -5,13 +5,10 @@
 
 namespace pics {
 
-// Columns per column tile: 16 up to length 320 (a build option), 4 at 512
-// (a single large slice then still gives the chip enough workgroups), 8 at
-// 1024.
-#ifndef PICS_COLT
-#define PICS_COLT 16
-#endif
-constexpr int kColT = PICS_COLT;
+// Columns per column tile: 16 up to length 320 (128-byte row segments), 4 at
+// 512 (a single large slice then still gives the chip enough workgroups), 8
+// at 1024.
+constexpr int kColT = 16;
 __host__ __device__ constexpr int col_tile(int m) { return m >= 1024 ? 8 : m >= 512 ? 4 : kColT; }
 // The fused operator's alternative tile widths (autotuner candidates besides
 // col_tile(m)), two per length, each giving workgroups of 64 to 1024 threads:
