@@ -263,20 +263,26 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   if (threadIdx.x < COUT) out[nw + threadIdx.x] = bias;
 }
 
-// grad[j] = sum_i part[i][j], j < count: per column four interleaved row
-// groups (rows i = grp, grp + 4, ...) summed in FP64, then added in group
-// order (a fixed order for a given row count)
-__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int rows, int count,
+// grad[j] = sum_i part[i][j], j < count: a workgroup takes C adjacent columns
+// (C = 16, 32 or 64, fewer for short gradients) and 256 / C interleaved row
+// groups per column (rows i = grp, grp + 256 / C, ...), each summed in FP64,
+// then added in group order (a fixed order for a given row count and C)
+__global__ __launch_bounds__(256) void k_reduce_rows(const float* __restrict__ part, int rows, int count, int C,
                                                      float* __restrict__ grad) {
-  __shared__ double sacc[4][64];
-  const int jl = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + jl;
+  __shared__ double sacc[256];
+  const int NG = 256 / C;
+  const int jl = threadIdx.x % C, grp = threadIdx.x / C;
+  const int j = blockIdx.x * C + jl;
   double acc = 0.0;
   if (j < count)
-    for (int i = grp; i < rows; i += 4) acc += part[(long long)i * count + j];
-  sacc[grp][jl] = acc;
+    for (int i = grp; i < rows; i += NG) acc += part[(long long)i * count + j];
+  sacc[threadIdx.x] = acc;
   __syncthreads();
-  if (grp == 0 && j < count) grad[j] = (float)(((sacc[0][jl] + sacc[1][jl]) + sacc[2][jl]) + sacc[3][jl]);
+  if (grp == 0 && j < count) {
+    double tot = sacc[jl];
+    for (int g = 1; g < NG; ++g) tot += sacc[g * C + jl];
+    grad[j] = (float)tot;
+  }
 }
 
 // --------------------------------------------------------------- the head
@@ -466,7 +472,8 @@ hipError_t launch_conv_bwd_w(hipStream_t st, int cinp, int cin, int cout, const 
 }
 
 hipError_t launch_reduce_rows(hipStream_t st, const float* part, int rows, int count, float* grad) {
-  hipLaunchKernelGGL(k_reduce_rows, dim3((count + 63) / 64), dim3(256), 0, st, part, rows, count, grad);
+  const int C = count >= 64 ? 64 : count >= 32 ? 32 : 16;
+  hipLaunchKernelGGL(k_reduce_rows, dim3((count + C - 1) / C), dim3(256), 0, st, part, rows, count, C, grad);
   return hipGetLastError();
 }
 
