@@ -22,7 +22,9 @@ Modules
 Parity status: every function here is pinned by the CPU tests against a dense
 matrix built from the definition, a closed form, an invariant or a library
 routine.  Split Bregman is pinned by closed-form scalar recurrences with inactive
-shrinks and with active wavelet shrinks.  With active TV shrinks it is pinned only
-piecewise: its operators, the shrink, and those recurrences.  That whole
-trajectory is "parity unpinned".
+shrinks and with active wavelet shrinks, and with active TV shrinks by its
+limit: the inner loop reaches the minimiser of the convex objective that an
+independent dual projected-gradient solve computes.  The learned correction's
+training trajectory (minibatch order, Adam state over many steps) is pinned only
+step by step.
 """
