@@ -160,3 +160,35 @@ def test_mixed_line_and_2d_batch_equals_per_slice(torch, B):
         it1, _, _, _ = c1.pcg_solve(b1, x1, 1e-3, 100)
         assert it1[0] == it_b[i]
         assert np.array_equal(_host(x1), xb[offs[i]:offs[i + 1]])
+
+
+@pytest.mark.parametrize("shapes", [[(128, 128, 8), (192, 192, 6), (320, 320, 5)], [(512, 512, 4), (128, 320, 3)]],
+                         ids=["128-192-320", "512-rect"])
+def test_2d_operator_and_spectrum_every_length(torch, B, shapes):
+    """The three-pass 2D-mask operator and the 2D correlation spectrum at the
+    transform lengths the other 2D tests do not reach (128, 192, 320, 512, and a
+    rectangular 128 x 320 slice), several sizes in one context, against the
+    oracle within 1e-5."""
+    _say(f"2d mask: operator and k at {shapes}")
+    insts = []
+    for i, (m, n, nc) in enumerate(shapes):
+        spec = gen.SliceSpec(m, n, nc, 4.0, max(4, m // 16), mask_kind="2d", wavelet="haar", levels=1)
+        insts.append(gen.make_instance(spec, gen.eval_seed(24, i + 10 * len(shapes))))
+    ctx, _ = B.context_for(insts)
+    xs = [gen.random_image(1900 + i, it.spec.m, it.spec.n) for i, it in enumerate(insts)]
+    xd = B.to_device(B.pack_images(xs))
+    yd = torch.empty_like(xd)
+    ctx.apply_A(xd, yd, B.TERM_ALL)
+    got = B.unpack_images(_host(yd), [(it.spec.m, it.spec.n) for it in insts])
+    khat = torch.empty(ctx.image_elems, dtype=torch.float32, device="cuda")
+    ctx.build_preconditioner("circulant", khat=khat)
+    kg = B.unpack_images(_host(khat), [(it.spec.m, it.spec.n) for it in insts])
+    for it, x, g, k in zip(insts, xs, got, kg):
+        s = it.spec
+        r2d = it.mask2d.astype(np.float64)
+        e_op = H.rel_err(g, ops.apply_A(x, it.sens, r2d, s.mu, s.lam, s.gam))
+        kref = opre.circulant_k(it.sens, r2d, s.mu, s.lam, s.gam)
+        e_k = np.max(np.abs(k - kref)) / np.max(np.abs(kref))
+        _say(f"  {s.m}x{s.n}x{s.ncoils}: operator {e_op:.2e}, k {e_k:.2e}")
+        assert e_op < 1e-5 and e_k < 1e-5, (s.m, s.n, e_op, e_k)
+    ctx.close()
